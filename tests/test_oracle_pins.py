@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Runs on the CPU only.  Every test here checks the oracle against something
+other than itself: values printed by the paper (Tables 1-3, the size orders of
+Sec. 6), the published SplitMix64 outputs, hand traces derived from the
+definitions of Sec. 2, the closed form of the sorting family, brute force over
+enumerated tiny systems against the dense matrix formulation, and invariants.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from oracle import oracle as orc
+from paper_2408_04343_amd import workloads as wl
+from tests._golden import int_matrix, lines
+
+STD, PK = orc.SEM_STANDARD, orc.SEM_PAPER_KERNEL
+FIRST, HASH = orc.SEL_FIRST, orc.SEL_HASH
+
+
+def make(spec, sem=STD, sel=None, seed=None):
+    return orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, sem,
+                            spec.select if sel is None else sel,
+                            spec.seed if seed is None else seed)
+
+
+# ---------------------------------------------------------------- hash ----
+
+def test_splitmix64_published_outputs():
+    rows = [ln.split() for ln in lines("splitmix64_kat.txt")]
+    G = 0x9E3779B97F4A7C15
+    for k, (state, out) in enumerate(rows, start=1):
+        assert int(state, 16) == (k * G) & ((1 << 64) - 1)
+        assert orc.mix64(int(state, 16)) == int(out, 16)
+
+
+def test_pick_power_of_two_is_top_bits():
+    # multiply-shift reduction: for a = 2^j the pick is the top j bits of h>>32
+    rng = np.random.default_rng(0)
+    for h in rng.integers(0, 2 ** 63, size=200, dtype=np.int64):
+        h = int(h) * 2 + 1
+        for j in range(0, 9):
+            assert orc.pick(h, 1 << j) == ((h >> 32) >> (32 - j) if j else 0)
+
+
+def test_pick_in_range_and_roughly_uniform():
+    counts = np.zeros(3, np.int64)
+    for k in range(60):
+        for i in range(100):
+            x = orc.pick(orc.hash_key(12345, k, i), 3)
+            assert 0 <= x < 3
+            counts[x] += 1
+    # chi-square with 2 dof, 6000 draws: statistical sanity only
+    e = counts.sum() / 3
+    chi2 = float(((counts - e) ** 2 / e).sum())
+    assert chi2 < 20.0
+
+
+def test_hash_keys_depend_on_every_field():
+    base = orc.hash_key(1, 0, 0)
+    assert base != orc.hash_key(2, 0, 0)
+    assert base != orc.hash_key(1, 1, 0)
+    assert base != orc.hash_key(1, 0, 1)
+    assert orc.hash_key(1, 1, 0) != orc.hash_key(1, 0, 1)
+
+
+# ------------------------------------------------------- paper tables ----
+
+def test_table1_transition_matrix_sort3():
+    spec = wl.sort_system([3, 1, 2])
+    M = dense.transition_matrix(spec.q, spec.rules, zip(spec.src, spec.dst))
+    assert M.tolist() == int_matrix("table1_sort3_M.txt")
+    # 108 elements, 75% zeros (Sec. 4)
+    assert M.size == 108
+    assert (M == 0).sum() == 81
+
+
+def _parse_ell():
+    nid, val = [], []
+    for ln in lines("table2_sort3_ell.txt"):
+        rn, rv = [], []
+        for tok in ln.split():
+            if tok == "-":
+                rn.append(-1); rv.append(0)
+            else:
+                v, n = tok.split(":")
+                rn.append(int(n)); rv.append(int(v))
+        nid.append(rn); val.append(rv)
+    return np.array(nid), np.array(val)
+
+
+def test_table2_ell_sort3():
+    spec = wl.sort_system([3, 1, 2])
+    o = make(spec)
+    nid, val = o.ell()
+    gn, gv = _parse_ell()
+    assert nid.shape == (4, 12)
+    assert np.array_equal(nid, gn)
+    assert np.array_equal(val, gv)
+
+
+def test_table3_sy_sort3():
+    spec = wl.sort_system([3, 1, 2])
+    o = make(spec)
+    assert o.sy().tolist() == int_matrix("table3_sort3_sy.txt")
+
+
+def test_paper_size_orders():
+    for ln in lines("paper_sizes.txt"):
+        fam, n, q, m, z, sp, el, co = ln.split()
+        n, q, m, z = int(n), int(q), int(m), int(z)
+        if fam == "sort":
+            assert (q, m, z) == (3 * n, n + n * n, n)
+        assert orc.paper_sizes(q, m, z) == (int(sp), int(el), int(co))
+
+
+def test_sort_family_structure_matches_size_formula():
+    for n in (3, 7, 20):
+        spec = wl.sort_system(list(range(n, 0, -1)))
+        assert (spec.q, spec.m, spec.max_outdeg()) == (3 * n, n + n * n, n)
+
+
+# --------------------------------------------------------- hand traces ----
+
+def _h1():
+    rules = [(0, 1, 0, 1, 1, 2), (1, 1, 0, 1, 1, 0)]
+    return 3, [1, 1, 0], rules, [0, 1, 1], [1, 0, 2]
+
+
+@pytest.mark.parametrize("mode,sem", [("standard", STD), ("paper_kernel", PK)])
+def test_hand_trace_h1(mode, sem):
+    q, s0, rules, src, dst = _h1()
+    rows = [ln for ln in lines("h1_trace.txt") if ln.split()[0] == mode]
+    o = orc.OracleSystem(q, s0, rules, src, dst, sem, FIRST, 0)
+    for ln in rows:
+        head, C, D, S = [x.strip() for x in ln.split("|")]
+        k = int(head.split()[1])
+        assert o.steps_done == k
+        st = o.read()
+        assert st["C"].tolist() == [int(x) for x in C.split()]
+        assert st["D"].tolist() == [int(x) for x in D.split()]
+        if S == "halted":
+            assert o.halted
+            assert o.step(5) == 0
+            assert o.steps_done == k
+            continue
+        rec = o.step_record(1)
+        assert rec["steps"] == 1
+        assert rec["S"][0].tolist() == [int(x) for x in S.split()]
+    if mode == "standard":
+        assert not o.halted
+
+
+def _h2(sel, seed):
+    # one neuron, no synapses, C0 = 4; rules a^3 (c3), a^2(a^2)* (c2), a(a)* (c1), a^4 (c4)
+    rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
+    return orc.OracleSystem(1, [4], rules, [], [], STD, sel, seed)
+
+
+def test_hand_trace_h2_first():
+    o = _h2(FIRST, 0)
+    rec = o.step_record(10)
+    assert rec["steps"] == 2
+    assert rec["S"][:, 0].tolist() == [1, 1]
+    assert rec["C"][:, 0].tolist() == [2, 0]
+    assert o.halted
+
+
+def test_hand_trace_h2_hash():
+    o = _h2(HASH, 1)
+    # state 0 (C=4): applicable, in id order: r1, r2, r3
+    j0 = orc.pick(orc.hash_key(1, 0, 0), 3)
+    # state after that: C = 4 - c; then the applicable set of the new count
+    first = [1, 2, 3][j0]
+    c_after = 4 - [3, 2, 1, 4][first]
+    appl = {2: [1], 3: [0, 2], 0: []}[c_after]
+    rec = o.step_record(10)
+    assert rec["S"][0, 0] == first
+    assert rec["C"][0, 0] == c_after
+    if appl:
+        j1 = orc.pick(orc.hash_key(1, 1, 0), len(appl))
+        assert rec["S"][1, 0] == appl[j1]
+    # with seed 1 the published-hash values give r2 then r0: 4 -> 3 -> 0
+    assert (j0, first, c_after) == (1, 2, 3)
+    assert rec["S"][:, 0].tolist() == [2, 0]
+    assert rec["steps"] == 2 and o.halted
+
+
+# ------------------------------------------------- sort-n closed form ----
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sort_family_closed_form(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 12))
+    v = rng.integers(0, 15, size=n).tolist()
+    spec = wl.sort_system(v)
+    results = []
+    for sem in (STD, PK):
+        for sel in (FIRST, HASH):
+            o = make(spec, sem, sel, seed=seed + 7)
+            done = o.step(10_000)
+            st = o.read()
+            assert done == max(v) + 1 if max(v) > 0 else done == 0
+            assert st["C"][2 * n:].tolist() == sorted(v)
+            assert st["C"][:2 * n].tolist() == [0] * (2 * n)
+            assert o.halted
+            results.append((done, st["C"].tolist()))
+    assert all(r == results[0] for r in results)
+
+
+def test_sort_worst_case_input_n100():
+    v = list(range(100, 0, -1))           # the paper's worst-case input (Sec. 6)
+    o = make(wl.sort_system(v))
+    assert o.step(1000) == 101
+    assert o.read()["C"][200:].tolist() == list(range(1, 101))
+
+
+# ------------------------------------------------- brute force vs dense ----
+
+def _tiny_systems():
+    """All systems with q = 2 on a fixed grid of parameters plus q = 3 samples."""
+    exprs = [(1, 0), (2, 0), (1, 1), (0, 1), (2, 2)]     # a, a^2, a+, a*, a^2(a^2)*
+    for e0, e1 in itertools.product(exprs, repeat=2):
+        for d0, d1 in ((0, 0), (1, 0), (2, 1)):
+            for c0 in ((2, 1), (3, 0), (1, 3)):
+                rules = [(0, e0[0], e0[1], max(1, e0[0]), 1, d0),
+                         (1, e1[0], e1[1], max(1, e1[0]), 2, d1)]
+                if e0 == (2, 2):
+                    rules.append((0, 1, 1, 1, 1, 0))
+                yield 2, list(c0), rules, [0, 1], [1, 0]
+    rng = np.random.default_rng(5)
+    for t in range(150):
+        spec = wl.small_random(1000 + t, 3, max_deg=2, max_rules=3, dmax=2, c0max=4)
+        yield 3, spec.spikes0.tolist(), spec.rules.tolist(), spec.src.tolist(), spec.dst.tolist()
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+@pytest.mark.parametrize("sel", [FIRST, HASH])
+def test_brute_force_against_dense_matrix(sem, sel):
+    n = 0
+    for q, c0, rules, src, dst in _tiny_systems():
+        seed = 77 + n
+        o = orc.OracleSystem(q, c0, rules, src, dst, sem, sel, seed)
+        d = dense.DenseSystem(q, c0, rules, list(zip(src, dst)), sem, sel, seed)
+        rec = o.step_record(8)
+        dsteps = 0
+        for t in range(8):
+            if not d.step():
+                break
+            dsteps += 1
+            assert rec["C"][t].tolist() == d.C.tolist(), (q, c0, rules, t)
+            assert rec["D"][t].tolist() == d.D.tolist()
+            assert rec["S"][t].tolist() == d.S.tolist()
+        assert rec["steps"] == dsteps
+        n += 1
+    assert n > 300
+
+
+def _valid_spiking_vectors(C, D, rules, q):
+    """Every valid choice: each open neuron with an applicable rule picks one."""
+    per = []
+    for i in range(q):
+        if D[i] != 0:
+            per.append([-1])
+            continue
+        a = [r for r, x in enumerate(rules) if x[0] == i and
+             dense.applicable_matrix(C, [x])[0]]
+        per.append(a if a else [-1])
+    return set(itertools.product(*per))
+
+
+def test_selection_is_a_valid_spiking_vector():
+    for t in range(60):
+        spec = wl.small_random(300 + t, 4, max_deg=3, max_rules=3, dmax=2, c0max=5)
+        for sel in (FIRST, HASH):
+            o = make(spec, STD, sel)
+            for _ in range(10):
+                st = o.read()
+                if o.halted:
+                    break
+                valid = _valid_spiking_vectors(st["C"], st["D"], spec.rules.tolist(), spec.q)
+                rec = o.step_record(1)
+                S = tuple(rec["S"][0].tolist())
+                assert S in valid
+                if sel == FIRST:
+                    assert S == tuple(min(v) if v != [-1] else -1 for v in
+                                      [sorted({s[i] for s in valid}) for i in range(spec.q)])
+
+
+# ---------------------------------------------------------- invariants ----
+
+def _conservation_check(spec, sem, sel, steps):
+    o = make(spec, sem, sel)
+    prev = o.read()["C"].astype(np.int64)
+    c_of = spec.rules[:, 3].astype(np.int64)
+    dmax = int(spec.rules[:, 5].max()) if spec.m else 0
+    rec = o.step_record(steps)
+    for t in range(rec["steps"]):
+        C, D, S = rec["C"][t].astype(np.int64), rec["D"][t], rec["S"][t]
+        cnt = rec["counters"][t]
+        cons = int(c_of[S[S >= 0]].sum())
+        assert C.sum() - prev.sum() == cnt["spikes_sent"] - cnt["spikes_lost"] - cons
+        assert (C >= 0).all()
+        assert ((D >= 0) & (D <= dmax)).all()
+        sel_rules = S[S >= 0]
+        assert (spec.rules[sel_rules, 0] == np.nonzero(S >= 0)[0]).all()
+        prev = C
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_spike_conservation_config1(sem):
+    _conservation_check(wl.config1(steps=100), sem, FIRST, 100)
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_spike_conservation_hash(sem):
+    spec = wl.small_random(11, 500, max_deg=6, max_rules=4, dmax=3, c0max=8)
+    _conservation_check(spec, sem, HASH, 60)
+
+
+def test_zero_delay_modes_coincide():
+    spec = wl.config1(steps=50)
+    spec.rules[:, 5] = 0
+    a = make(spec, STD).step_record(50)
+    b = make(spec, PK).step_record(50)
+    for key in ("C", "D", "S"):
+        assert np.array_equal(a[key], b[key])
+    assert (a["D"] == 0).all()
+
+
+def test_no_synapses_each_neuron_alone():
+    # a+/a -> a with delay d: a neuron with n spikes fires once per (d+1) steps
+    # in STANDARD mode and empties after n firings: at step t (0-based) it
+    # holds n - ceil(t / (d+1)) spikes, floored at 0.
+    q = 6
+    for d in (0, 1, 3):
+        s0 = [0, 1, 2, 5, 7, 3]
+        rules = [(i, 1, 1, 1, 1, d) for i in range(q)]
+        o = orc.OracleSystem(q, s0, rules, [], [], STD, FIRST, 0)
+        rec = o.step_record(40)
+        for t in range(rec["steps"]):
+            k = t + 1
+            exp = [max(0, n - (-(-k // (d + 1)))) for n in s0]
+            assert rec["C"][t].tolist() == exp
+
+
+def test_halting_is_absorbing():
+    spec = wl.sort_system([2, 5, 1])
+    o = make(spec)
+    done = o.step(100)
+    st = o.read()
+    assert o.halted and done == 6
+    assert o.step(10) == 0
+    assert o.steps_done == 6
+    st2 = o.read()
+    for k in ("C", "D", "S"):
+        assert np.array_equal(st[k], st2[k])
+
+
+def test_digest_definition():
+    spec = wl.small_random(3, 40, c0max=9)
+    o = make(spec)
+    o.step(5)
+    st = o.read()
+    G = 0x9E3779B97F4A7C15
+    M = (1 << 64) - 1
+    acc = 0
+    for i in range(spec.q):
+        key = (i * G) & M
+        cd = ((int(st["C"][i]) & 0xFFFFFFFF) << 32) | (int(st["D"][i]) & 0xFFFFFFFF)
+        acc += dense._mix64(key ^ cd)
+        acc += dense._mix64((~key & M) ^ (int(st["S"][i]) & 0xFFFFFFFF))
+    assert o.digest() == acc & M
+
+
+# ---------------------------------------------------------- validation ----
+
+@pytest.mark.parametrize("bad", [
+    dict(src=[0], dst=[0]),                      # reflexive synapse
+    dict(src=[0, 0], dst=[1, 1]),                # repeated synapse
+    dict(src=[0], dst=[5]),                      # out of range
+    dict(rules=[(0, 1, 0, 0, 1, 0)]),            # c < 1
+    dict(rules=[(0, 1, 0, 1, -1, 0)]),           # p < 0
+    dict(rules=[(0, 1, 0, 1, 1, -1)]),           # d < 0
+    dict(rules=[(3, 1, 0, 1, 1, 0)]),            # neuron out of range
+    dict(s0=[-1, 0]),                            # negative spikes
+])
+def test_invalid_systems_rejected(bad):
+    kw = dict(s0=[1, 1], rules=[(0, 1, 0, 1, 1, 0)], src=[0], dst=[1])
+    kw.update(bad)
+    with pytest.raises(orc.OracleError):
+        orc.OracleSystem(2, kw["s0"], kw["rules"], kw["src"], kw["dst"])
+
+
+def test_overflow_flag():
+    big = 2 ** 31 - 2
+    o = orc.OracleSystem(2, [1, big], [(0, 1, 0, 1, 5, 0)], [0], [1])
+    o.step(1)
+    assert o.overflow
+    o2 = orc.OracleSystem(2, [1, big - 10], [(0, 1, 0, 1, 5, 0)], [0], [1])
+    o2.step(1)
+    assert not o2.overflow
+    assert o2.read_c64()[1] == big - 5
