@@ -1,0 +1,246 @@
+/*
+ * snp.h -- C ABI of the MI355X (gfx950) simulator of Spiking Neural P systems
+ * with delays.
+ *
+ * The operations follow Hernandez-Tello, Martinez-del-Amor, Orellana-Martin
+ * and Cabarle, "Sparse Spiking Neural-like Membrane Systems on Graphics
+ * Processing Units", Int. J. Neural Systems 34(7) 2450038 (2024):
+ *   - a system Pi = (O, syn, sigma_1..sigma_q, i_out) is given by the initial
+ *     spikes of each neuron, its rules E/a^c -> a^p; d and the synapse set
+ *     syn (Sec. 2; the three-step definition of Sec. 5.1);
+ *   - one computation repeats SV_CALC, SAMPLE_ONE, STEP and UPDATE_DELAYS
+ *     until a step limit or until no rule applies and every neuron is open
+ *     (Sec. 2, Alg. 1; Sec. 5.2);
+ *   - the transition matrix is stored as ELL (Sec. 4, Table 2), as the
+ *     compressed / "Optimized" synapse matrix Sy plus p in the rule vector
+ *     (Sec. 4, Table 3), or as CSR (Sec. 3).
+ *
+ * Every function returns an int status: SNP_OK (0) or a negative SNP_E*
+ * code.  No C++ exception crosses the ABI.  All pointers named "host" are
+ * host memory owned by the caller; the library copies what it needs before
+ * returning.  Device memory belongs to the handle until snp_destroy.
+ * A handle is not thread-safe; different handles may be driven from
+ * different threads and streams.
+ */
+#ifndef SNP_H_
+#define SNP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define SNP_OK         0
+#define SNP_EINVAL    (-1) /* invalid argument or invalid system            */
+#define SNP_ENOMEM    (-2) /* device or host allocation failed              */
+#define SNP_EDEVICE   (-3) /* a HIP runtime call failed (see snp_last_error) */
+#define SNP_EOVERFLOW (-4) /* a spike count left the int32 range (sticky)   */
+#define SNP_EBUSY     (-5) /* the handle is a member of a batch             */
+#define SNP_ENOTSUP   (-6) /* valid system outside the supported limits     */
+
+/* ---- options ------------------------------------------------------------ */
+/* Representation of the transition matrix (Sec. 4):
+ *   OPTIMIZED  Sy_Pi: z = MaxOutDegree rows x q columns of target ids, -1
+ *              padding; p taken from the rule vector (Table 3).
+ *   ELL        M^s_Pi: z' = MaxOutDegree + 1 rows x m columns of
+ *              (neuron, value) pairs; row 0 = (own neuron, -c), then
+ *              (target, +p), then (-1, 0) padding (Table 2).
+ *   CSR_PUSH   out-neighbour lists (row starts + target ids, Sec. 3); spikes
+ *              are pushed to targets.
+ *   CSR_PULL   in-neighbour lists; each target gathers what its
+ *              in-neighbours emitted (no atomics).
+ *   AUTO       CSR_PULL.                                                   */
+#define SNP_LAYOUT_AUTO      0
+#define SNP_LAYOUT_OPTIMIZED 1
+#define SNP_LAYOUT_ELL       2
+#define SNP_LAYOUT_CSR_PUSH  3
+#define SNP_LAYOUT_CSR_PULL  4
+
+/* Choice among the applicable rules of an open neuron (Sec. 5.2 replaces
+ * SAMPLE_ONE by the first applicable rule):
+ *   FIRST  lowest rule id;
+ *   HASH   the j-th applicable rule in increasing id, j = pick(h, count) with
+ *          h = mix64(mix64(seed) xor (k << 32 | i)) for system-local step k
+ *          and neuron i, mix64 = SplitMix64 output function, pick(h, a) =
+ *          ((h >> 32) * a) >> 32.                                          */
+#define SNP_SELECT_FIRST 0
+#define SNP_SELECT_HASH  1
+
+/* Delay semantics (d of E/a^c -> a^p; d, Sec. 2):
+ *   STANDARD      a rule with delay d selected at step k consumes c at once,
+ *                 keeps the neuron closed for steps k..k+d-1 (spikes sent to
+ *                 it are lost) and sends its p spikes at step k+d, when the
+ *                 neuron opens again.
+ *   PAPER_KERNEL  the transition kernels as printed (Alg. 3-5): the spikes
+ *                 leave at selection, only neurons open at the start of the
+ *                 step receive, and the neuron is closed for the next d steps.
+ * Both coincide when every d = 0.                                           */
+#define SNP_SEM_STANDARD     0
+#define SNP_SEM_PAPER_KERNEL 1
+
+/* flags */
+#define SNP_F_DIGEST   0x1u /* keep a digest of every reached state          */
+#define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
+#define SNP_F_NO_GRAPH 0x4u /* launch step kernels one by one (no hipGraph)  */
+
+/* Device memory hooks (e.g. a framework's caching allocator).  `stream` is
+ * the handle's hipStream_t.  NULL hooks = hipMalloc / hipFree.            */
+typedef void* (*snp_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*snp_free_fn)(void* ctx, void* ptr, void* stream);
+
+typedef struct snp_opts {
+  int32_t layout;      /* SNP_LAYOUT_*                                       */
+  int32_t select;      /* SNP_SELECT_*                                       */
+  int32_t semantics;   /* SNP_SEM_*                                          */
+  int32_t chunk;       /* steps per captured graph; 0 = 64                   */
+  uint64_t seed;       /* key of the HASH choice                             */
+  void* stream;        /* hipStream_t to run on; NULL = the library creates a
+                          non-blocking stream of default priority            */
+  uint32_t flags;      /* SNP_F_*                                            */
+  int32_t device;      /* HIP device ordinal; -1 = current device            */
+  int64_t ring;        /* entries kept by the digest / counter rings; 0 = 4096 */
+  snp_alloc_fn alloc;
+  snp_free_fn free;
+  void* alloc_ctx;
+} snp_opts;
+
+/* A rule E/a^c -> a^p; d of neuron `neuron`, with E = a^base (a^period)*
+ * and period 0 meaning exactly a^base.  The paper's regular-expression types
+ * map to (base, period) as: a* -> (0, 1); a+ -> (1, 1); a^n -> (n, 0); type
+ * four a^i(a^j)* -> (i, j) and a^i(a^j)+ -> (i + j, j) (Sec. 2, Sec. 7).  A
+ * forgetting rule a^s -> lambda is (s, 0) with c = s and p = 0 (Sec. 4).  A
+ * rule applies when its expression covers the neuron's count n and n >= c.
+ * The rule id of a rule is its index in the caller's array; among the rules
+ * of one neuron a lower id has priority (FIRST).                          */
+typedef struct snp_rule {
+  int32_t neuron, base, period, c, p, d;
+} snp_rule;
+
+/* Per-step work counters (SNP_F_COUNTERS), one record per executed step. */
+typedef struct snp_counters {
+  int64_t open_neurons;  /* neurons with D = 0 at the start of the step      */
+  int64_t rules_of_open; /* rules owned by open neurons                      */
+  int64_t selecting;     /* open neurons that selected a rule                */
+  int64_t emitting;      /* neurons whose spikes leave at this step          */
+  int64_t emit_edges;    /* sum of the out-degrees of the emitting neurons   */
+  int64_t spikes_sent;   /* sum over emitting s of p_s * deg(s)              */
+  int64_t spikes_lost;   /* of those, spikes that reached a closed neuron    */
+  int64_t receiving;     /* neurons open for reception at this step          */
+  int64_t reopening;     /* neurons whose delay counter reached zero         */
+} snp_counters;
+
+typedef struct snp_sys snp_sys;
+
+/* Fills *opts with the defaults (AUTO layout, FIRST, STANDARD, chunk 64). */
+void snp_opts_default(snp_opts* opts);
+
+/* INIT of Alg. 1 (Sec. 2) and the model definition of Sec. 5.1: builds the
+ * configuration vector C_0 = spikes0, the rule vector RV and neuron-rule map
+ * N, the delays vector D_0 = 0 and the chosen representation of the
+ * transition matrix, on the device.
+ *   q        number of neurons (>= 1)
+ *   spikes0  host [q] initial spikes (>= 0)
+ *   m        number of rules (>= 0);  rules  host [m]
+ *   nsyn     number of synapses (>= 0); syn_src / syn_dst host [nsyn]
+ *   opts     NULL = defaults
+ *   out      receives the handle
+ * SNP_EINVAL: q < 1, spikes0[i] < 0, a rule neuron outside [0, q),
+ *   base < 0, period < 0, c < 1, p < 0, d < 0, a synapse endpoint outside
+ *   [0, q), a synapse (i, i) (reflexive synapses are not allowed, Sec. 2) or
+ *   a repeated synapse (syn is a set, Sec. 2).
+ * SNP_ENOTSUP: p or d above 65535, more than 65535 rules on one neuron, more
+ *   than 2^31 - 1 synapses, or a neuron whose in-neighbours could send it
+ *   2^31 or more spikes in one step.
+ * SNP_ENOMEM: the representation does not fit in device memory.          */
+int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rules,
+               int64_t nsyn, const int32_t* syn_src, const int32_t* syn_dst,
+               const snp_opts* opts, snp_sys** out);
+
+/* Enqueues k more transition steps on the handle's stream and returns
+ * without waiting.  Steps after the system halts do nothing (halting is
+ * absorbing).  k <= 0 does nothing.                                        */
+int snp_step(snp_sys* sys, int64_t k);
+
+/* Waits for the stream, then reports the number of executed steps and
+ * whether the current configuration is halted (no rule applicable in any
+ * open neuron and every neuron open).  Either pointer may be NULL.
+ * Returns SNP_EOVERFLOW if a count ever left the int32 range.              */
+int snp_steps_done(snp_sys* sys, int64_t* steps, int32_t* halted);
+
+/* Wait for the stream, then copy the current configuration vector C_k
+ * (host [q]).                                                              */
+int snp_read_config(snp_sys* sys, int32_t* out);
+
+/* Spiking vector of the last executed step in neuron form (Sec. 4,
+ * Compressed): out[i] = caller id of the rule selected by neuron i, -1 if
+ * none (host [q]).  All -1 before the first step.                          */
+int snp_read_spiking(snp_sys* sys, int32_t* out);
+
+/* Delays vector D_k: 0 = open, > 0 = steps until the neuron opens (host [q]). */
+int snp_read_delays(snp_sys* sys, int32_t* out);
+
+/* Rule whose spikes are still to be sent (STANDARD mode, D > 0), -1 if none
+ * (host [q]).                                                              */
+int snp_read_pending(snp_sys* sys, int32_t* out);
+
+/* Digest of the current state (C_k, D_k, S_{k-1}):
+ *   sum_i mix64(i*G xor (C_i << 32 | D_i)) + sum_i mix64(~(i*G) xor S_i)
+ * mod 2^64, G = 0x9E3779B97F4A7C15, computed on the device.               */
+int snp_digest(snp_sys* sys, uint64_t* out);
+
+/* With SNP_F_DIGEST: digests of the states reached after steps
+ * first+1 .. first+count (host [count]); the ring keeps the last `ring`
+ * entries.  SNP_EINVAL if a requested entry is not in the ring.           */
+int snp_read_digests(snp_sys* sys, uint64_t* out, int64_t first, int64_t count);
+
+/* With SNP_F_COUNTERS: work counters of steps first .. first+count-1.      */
+int snp_read_counters(snp_sys* sys, snp_counters* out, int64_t first, int64_t count);
+
+/* Checkpoint restore: replaces the state by (C, D, pending, S) at step
+ * index k (host [q] each; `pending` and `spiking` may be NULL = none).
+ * Resuming from a state read with the snp_read_* calls gives the same
+ * computation as never stopping.                                          */
+int snp_write_state(snp_sys* sys, const int32_t* config, const int32_t* delays,
+                    const int32_t* pending, const int32_t* spiking, int64_t k);
+
+/* Device copy of the representation, for inspection (host buffers):
+ *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
+ *   which = SNP_LAYOUT_ELL: M^s as [z'][m][2] int32 (neuron, value), columns
+ *           in caller rule id order;
+ *   which = SNP_LAYOUT_CSR_PUSH: out-neighbour row starts [q+1] then targets.
+ * `count` is the capacity of `out` in int32 elements; `*needed` receives the
+ * size required.                                                           */
+int snp_read_layout(snp_sys* sys, int32_t which, int32_t* out, int64_t count, int64_t* needed);
+
+/* Shape of the handle: q, m, synapses, MaxOutDegree, layout in use. */
+int snp_info(snp_sys* sys, int32_t* q, int32_t* m, int64_t* nsyn, int32_t* zmax, int32_t* layout);
+
+/* Device bytes a system of this shape needs in `layout` with `flags` and a
+ * ring of `ring` entries (0 = 4096), as snp_create allocates them.        */
+int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layout,
+                  uint32_t flags, int64_t ring, int64_t* bytes);
+
+/* The paper's size order (number of elements) of the three representations
+ * of the transition matrix (Sec. 6): Sparse m q + 3m + 2q + 1, ELL
+ * m(2z + 5) + 2q + 1, Compressed q(z + 3) + 4m + 1.  Any pointer may be
+ * NULL.                                                                   */
+int snp_paper_sizes(int64_t q, int64_t m, int64_t z, int64_t* sparse, int64_t* ell,
+                    int64_t* compressed);
+
+/* Frees the handle and its device memory (waits for its stream). */
+int snp_destroy(snp_sys* sys);
+
+/* hipStream_t the handle runs on. */
+void* snp_stream(snp_sys* sys);
+
+/* Text of a status code / of the last error on this thread. */
+const char* snp_strerror(int status);
+const char* snp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNP_H_ */

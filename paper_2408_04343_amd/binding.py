@@ -1,0 +1,310 @@
+"""Thin ctypes binding of the C ABI in ``include/snp.h`` (argument marshalling
+only: every step of the simulation runs in the HIP library).
+
+Importing this module loads ``libsnp.so`` from the package directory, building
+it first with hipcc if it is missing; if that fails the import fails.  There
+is no CPU fallback.  PyTorch, when present with a GPU, supplies the device
+memory (its caching allocator, through the library's allocation hooks) and
+the stream each system runs on.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL = 0, 1, 2, 3, 4
+SELECT_FIRST, SELECT_HASH = 0, 1
+SEM_STANDARD, SEM_PAPER_KERNEL = 0, 1
+F_DIGEST, F_COUNTERS, F_NO_GRAPH = 0x1, 0x2, 0x4
+
+LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL,
+           "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL}
+SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
+SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
+
+# exported symbols, in header order
+SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_read_config",
+           "snp_read_spiking", "snp_read_delays", "snp_read_pending", "snp_digest",
+           "snp_read_digests", "snp_read_counters", "snp_write_state", "snp_read_layout",
+           "snp_info", "snp_footprint", "snp_paper_sizes", "snp_destroy", "snp_stream",
+           "snp_strerror", "snp_last_error"]
+
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
+FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
+
+
+class Opts(ct.Structure):
+    _fields_ = [("layout", ct.c_int32), ("select", ct.c_int32), ("semantics", ct.c_int32),
+                ("chunk", ct.c_int32), ("seed", ct.c_uint64), ("stream", ct.c_void_p),
+                ("flags", ct.c_uint32), ("device", ct.c_int32), ("ring", ct.c_int64),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ct.c_void_p)]
+
+
+class Rule(ct.Structure):
+    _fields_ = [("neuron", ct.c_int32), ("base", ct.c_int32), ("period", ct.c_int32),
+                ("c", ct.c_int32), ("p", ct.c_int32), ("d", ct.c_int32)]
+
+
+COUNTER_FIELDS = ["open_neurons", "rules_of_open", "selecting", "emitting", "emit_edges",
+                  "spikes_sent", "spikes_lost", "receiving", "reopening"]
+
+
+class Counters(ct.Structure):
+    _fields_ = [(n, ct.c_int64) for n in COUNTER_FIELDS]
+
+
+class SnpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d): %s" % (fn_strerror(status), status, msg))
+        self.status = status
+
+
+def _load():
+    path = _build.LIB
+    if not os.path.exists(path):
+        _build.build()
+    lib = ct.CDLL(path)
+    P = ct.POINTER
+    i32p, i64p, u64p = P(ct.c_int32), P(ct.c_int64), P(ct.c_uint64)
+    vp = ct.c_void_p
+    sig = {
+        "snp_opts_default": (None, [P(Opts)]),
+        "snp_create": (ct.c_int, [ct.c_int32, i32p, ct.c_int32, P(Rule), ct.c_int64, i32p, i32p,
+                                  P(Opts), P(vp)]),
+        "snp_step": (ct.c_int, [vp, ct.c_int64]),
+        "snp_steps_done": (ct.c_int, [vp, i64p, i32p]),
+        "snp_read_config": (ct.c_int, [vp, i32p]),
+        "snp_read_spiking": (ct.c_int, [vp, i32p]),
+        "snp_read_delays": (ct.c_int, [vp, i32p]),
+        "snp_read_pending": (ct.c_int, [vp, i32p]),
+        "snp_digest": (ct.c_int, [vp, u64p]),
+        "snp_read_digests": (ct.c_int, [vp, u64p, ct.c_int64, ct.c_int64]),
+        "snp_read_counters": (ct.c_int, [vp, P(Counters), ct.c_int64, ct.c_int64]),
+        "snp_write_state": (ct.c_int, [vp, i32p, i32p, i32p, i32p, ct.c_int64]),
+        "snp_read_layout": (ct.c_int, [vp, ct.c_int32, i32p, ct.c_int64, i64p]),
+        "snp_info": (ct.c_int, [vp, i32p, i32p, i64p, i32p, i32p]),
+        "snp_footprint": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
+                                     ct.c_uint32, ct.c_int64, i64p]),
+        "snp_paper_sizes": (ct.c_int, [ct.c_int64, ct.c_int64, ct.c_int64, i64p, i64p, i64p]),
+        "snp_destroy": (ct.c_int, [vp]),
+        "snp_stream": (vp, [vp]),
+        "snp_strerror": (ct.c_char_p, [ct.c_int]),
+        "snp_last_error": (ct.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def fn_strerror(status: int) -> str:
+    return lib.snp_strerror(status).decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise SnpError(status, lib.snp_last_error().decode())
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_int32))
+
+
+def footprint(q, m, nnz, z, layout="auto", flags=0, ring=0) -> int:
+    out = ct.c_int64()
+    _check(lib.snp_footprint(q, m, nnz, z, LAYOUTS.get(layout, layout), flags, ring, ct.byref(out)))
+    return int(out.value)
+
+
+def paper_sizes(q, m, z):
+    a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()
+    _check(lib.snp_paper_sizes(q, m, z, ct.byref(a), ct.byref(b), ct.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
+
+
+def _torch_cuda():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch
+    except Exception:
+        pass
+    return None
+
+
+class _TorchMemory:
+    """Device memory from torch's caching allocator, on the system's stream."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+
+        def alloc(_ctx, size, stream):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(size), self.device, int(stream or 0)))
+            except Exception:
+                return None
+
+        def free(_ctx, ptr, _stream):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+
+        self.alloc = ALLOC_FN(alloc)
+        self.free = FREE_FN(free)
+
+
+class System:
+    """One SNP system resident on the GPU (wraps an ``snp_sys`` handle)."""
+
+    def __init__(self, q, spikes0, rules, src, dst, *, layout="auto", select="first",
+                 semantics="standard", seed=0, chunk=64, digest=False, counters=False,
+                 graph=True, ring=0, device=None, memory="auto", stream=None):
+        self._h = ct.c_void_p()
+        self.q = int(q)
+        s0 = _i32(spikes0)
+        rr = _i32(rules).reshape(-1, 6)
+        self.m = int(rr.shape[0])
+        sa, da = _i32(src), _i32(dst)
+        if s0.shape != (self.q,) or sa.shape != da.shape:
+            raise ValueError("spikes0 must have q entries and src/dst the same length")
+        o = Opts()
+        lib.snp_opts_default(ct.byref(o))
+        o.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        o.select = SELECTS[select] if isinstance(select, str) else int(select)
+        o.semantics = SEMANTICS[semantics] if isinstance(semantics, str) else int(semantics)
+        o.chunk = int(chunk)
+        o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        o.flags = (F_DIGEST if digest else 0) | (F_COUNTERS if counters else 0) | (0 if graph else F_NO_GRAPH)
+        o.ring = int(ring)
+        o.device = -1 if device is None else int(device)
+        torch = _torch_cuda()
+        self._torch_stream = None
+        self._mem = None
+        if stream is not None:
+            o.stream = int(stream)
+        elif torch is not None:
+            dev = torch.cuda.current_device() if device is None else int(device)
+            self._torch_stream = torch.cuda.Stream(device=dev)
+            o.stream = self._torch_stream.cuda_stream
+        if memory == "auto":
+            memory = "torch" if torch is not None else "hip"
+        if memory == "torch":
+            if torch is None:
+                raise RuntimeError("memory='torch' needs torch with a GPU")
+            dev = torch.cuda.current_device() if device is None else int(device)
+            self._mem = _TorchMemory(torch, dev)
+            o.alloc, o.free = self._mem.alloc, self._mem.free
+        rules_c = (Rule * max(1, self.m))()
+        if self.m:
+            ct.memmove(rules_c, rr.ctypes.data, rr.nbytes)
+        _check(lib.snp_create(self.q, _ptr(s0), self.m, rules_c, len(sa), _ptr(sa), _ptr(da),
+                              ct.byref(o), ct.byref(self._h)))
+        self.layout_id = o.layout
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        kw.setdefault("select", spec.select)
+        kw.setdefault("seed", spec.seed)
+        return cls(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, **kw)
+
+    # ---- lifetime ----
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib.snp_destroy(self._h))
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def stream(self) -> int:
+        return int(lib.snp_stream(self._h) or 0)
+
+    # ---- stepping ----
+    def step(self, k: int):
+        _check(lib.snp_step(self._h, int(k)))
+
+    def steps_done(self):
+        steps, halted = ct.c_int64(), ct.c_int32()
+        _check(lib.snp_steps_done(self._h, ct.byref(steps), ct.byref(halted)))
+        return int(steps.value), bool(halted.value)
+
+    def _read(self, fn):
+        out = np.empty(self.q, np.int32)
+        _check(fn(self._h, _ptr(out)))
+        return out
+
+    def read_config(self):
+        return self._read(lib.snp_read_config)
+
+    def read_spiking(self):
+        return self._read(lib.snp_read_spiking)
+
+    def read_delays(self):
+        return self._read(lib.snp_read_delays)
+
+    def read_pending(self):
+        return self._read(lib.snp_read_pending)
+
+    def digest(self) -> int:
+        v = ct.c_uint64()
+        _check(lib.snp_digest(self._h, ct.byref(v)))
+        return int(v.value)
+
+    def read_digests(self, first: int, count: int):
+        out = np.empty(count, np.uint64)
+        _check(lib.snp_read_digests(self._h, out.ctypes.data_as(ct.POINTER(ct.c_uint64)), first, count))
+        return out
+
+    def read_counters(self, first: int, count: int):
+        arr = (Counters * max(1, count))()
+        _check(lib.snp_read_counters(self._h, arr, first, count))
+        return [{n: int(getattr(arr[t], n)) for n in COUNTER_FIELDS} for t in range(count)]
+
+    def write_state(self, config, delays, pending=None, spiking=None, k=0):
+        C, D = _i32(config), _i32(delays)
+        P = _i32(pending) if pending is not None else None
+        S = _i32(spiking) if spiking is not None else None
+        _check(lib.snp_write_state(self._h, _ptr(C), _ptr(D), _ptr(P) if P is not None else None,
+                                   _ptr(S) if S is not None else None, int(k)))
+
+    def read_layout(self, which):
+        which = LAYOUTS[which] if isinstance(which, str) else int(which)
+        need = ct.c_int64()
+        _check(lib.snp_read_layout(self._h, which, None, 0, ct.byref(need)))
+        out = np.empty(max(1, need.value), np.int32)
+        _check(lib.snp_read_layout(self._h, which, _ptr(out), need.value, ct.byref(need)))
+        return out[:need.value]
+
+    def info(self):
+        q, m, z, lay = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
+        n = ct.c_int64()
+        _check(lib.snp_info(self._h, ct.byref(q), ct.byref(m), ct.byref(n), ct.byref(z), ct.byref(lay)))
+        return {"q": q.value, "m": m.value, "nsyn": n.value, "zmax": z.value, "layout": lay.value}

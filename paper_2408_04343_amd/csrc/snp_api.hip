@@ -1,0 +1,791 @@
+// Host side of the C ABI declared in include/snp.h.
+//
+// snp_create validates the system (Sec. 2: no reflexive synapse, syn is a
+// set), permutes the rules into neuron order (the neuron-rule map N_Pi of
+// Sec. 2), builds the out- and in-neighbour lists on the host, uploads them
+// and expands the chosen representation of the transition matrix on the
+// device (Sec. 4; Tables 2 and 3).  snp_step enqueues step kernels, in
+// captured graphs of `chunk` steps when it can.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "snp.h"
+#include "snp_internal.h"
+
+using namespace snp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      return fail(e_ == hipErrorOutOfMemory ? SNP_ENOMEM : SNP_EDEVICE,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    }                                                                                 \
+  } while (0)
+
+constexpr int64_t kDefaultRing = 4096;
+constexpr int32_t kDefaultChunk = 64;
+constexpr int32_t kPullLdsBytes = 60 * 1024;  // LDS for one chunk of emitted values
+
+int32_t emit_width(int32_t pmax) {
+  int32_t w = 1;
+  while (w < 16 && pmax > (int32_t)((1u << w) - 1u)) w *= 2;
+  return w;
+}
+
+int32_t pull_chunk_sources(int32_t w) {
+  const int64_t stage = (int64_t)pull_tile() * w / 32 * 4;
+  int64_t words = (kPullLdsBytes - stage) / 4;
+  int64_t src = words * 32 / w;
+  src -= src % 32;
+  return (int32_t)std::max<int64_t>(32, src);
+}
+
+struct Plan {
+  int64_t bytes = 0;
+  void add(int64_t b) { bytes += (b + 255) / 256 * 256; }
+};
+
+// Device bytes of a system; mirrors the allocations of snp_create.
+int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout, uint32_t flags,
+                   int64_t ring, int32_t emit_w) {
+  Plan p;
+  p.add(4LL * q);            // C
+  p.add(4LL * q);            // meta
+  p.add(4LL * q);            // pend
+  p.add(2LL * q * 2);        // S16[2]
+  p.add(4LL * (q + 1));      // rs
+  p.add(16LL * m);           // rules
+  p.add(4LL * m);            // rid
+  p.add(4LL * m);            // slot of caller id
+  p.add(sizeof(Ctl));
+  p.add(4LL * q * 4);        // materialize outputs
+  p.add(16);                 // digest scratch
+  if (flags & SNP_F_DIGEST) p.add(8 * ring);
+  if (flags & SNP_F_COUNTERS) p.add(8LL * NCOUNT * (ring + 1));
+  if (layout == L_CSR_PULL) {
+    const int64_t tiles = (q + pull_tile() - 1) / pull_tile();
+    p.add(4LL * (q + 1));
+    p.add(4LL * std::max<int64_t>(nnz, 1));
+    p.add(2 * tiles * pull_tile() * emit_w / 32 * 4);
+    if (flags & SNP_F_COUNTERS) p.add(4LL * q);
+  } else {
+    p.add(4LL * q * 2);      // delta[2]
+    p.add(4LL * (q + 1));    // out_ptr
+    p.add(4LL * std::max<int64_t>(nnz, 1));
+    if (layout == L_OPT) p.add(4LL * z * q);
+    if (layout == L_ELL) p.add(8LL * (z + 1) * std::max(m, 1));
+  }
+  return p.bytes;
+}
+
+}  // namespace
+
+struct snp_sys {
+  snp_opts opts{};
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  SysDev d{};
+  int32_t q = 0, m = 0, z = 0, layout = 0;
+  int64_t nnz = 0;
+  std::vector<void*> allocs;
+  std::vector<int32_t> h_rid, h_slot, h_rs, h_out_ptr, h_out_col, h_in_ptr, h_in_src;
+  int32_t* scratch = nullptr;            // [4][q] materialized C, D, S, pend
+  unsigned long long* dig_tmp = nullptr;
+  int32_t* slot_of = nullptr;            // caller id -> slot
+  int32_t chunk = kDefaultChunk;
+  hipGraphExec_t graph = nullptr;
+  bool graph_tried = false;
+  int in_batch = 0;
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 4;
+    void* p = nullptr;
+    if (opts.alloc) {
+      p = opts.alloc(opts.alloc_ctx, bytes, (void*)stream);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  void release() {
+    if (graph) {
+      (void)hipGraphExecDestroy(graph);
+      graph = nullptr;
+    }
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) {
+      if (opts.free) opts.free(opts.alloc_ctx, p, (void*)stream);
+      else (void)hipFree(p);
+    }
+    allocs.clear();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    stream = nullptr;
+  }
+};
+
+namespace {
+
+struct DevScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DevScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) ok = false;
+    else if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DevScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+int upload(snp_sys* s, T** dst, const T* src, size_t n) {
+  *dst = (T*)s->dalloc(sizeof(T) * std::max<size_t>(n, 1));
+  if (!*dst) return fail(SNP_ENOMEM, "device allocation failed");
+  if (n) HIPCHK(hipMemcpyAsync(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice, s->stream));
+  return SNP_OK;
+}
+
+int alloc_fill(snp_sys* s, void** dst, size_t bytes, int byte) {
+  *dst = s->dalloc(bytes);
+  if (!*dst) return fail(SNP_ENOMEM, "device allocation failed");
+  HIPCHK(hipMemsetAsync(*dst, byte, bytes, s->stream));
+  return SNP_OK;
+}
+
+#define TRY(expr)               \
+  do {                          \
+    int st_ = (expr);           \
+    if (st_ != SNP_OK) return st_; \
+  } while (0)
+
+// Facts about the current state, read from the control block.
+struct StateInfo {
+  int64_t steps = 0;   // executed steps
+  int64_t kx = 0;      // step kernels whose body ran
+  bool halted_seen = false;
+  bool overflow = false;
+  int32_t rbuf = -1;   // receive buffer still to be added (last kernel's)
+  int32_t sbuf = -1;   // S16 buffer of the last executed step
+};
+
+int query(snp_sys* s, StateInfo* si) {
+  HIPCHK(hipStreamSynchronize(s->stream));
+  Ctl c;
+  HIPCHK(hipMemcpy(&c, s->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  si->kx = c.k_exec;
+  si->overflow = c.overflow != 0;
+  if (c.halted) {
+    si->steps = c.halt_step;
+    si->halted_seen = true;
+  } else if (c.k_exec >= 1 && c.active[(c.k_exec - 1) % 3] == 0) {
+    si->steps = c.k_exec - 1;
+    si->halted_seen = true;
+  } else {
+    si->steps = c.k_exec;
+  }
+  si->rbuf = si->kx >= 1 ? (int32_t)((si->kx - 1) & 1) : -1;
+  si->sbuf = si->steps >= 1 ? (int32_t)((si->steps - 1) & 1) : -1;
+  return SNP_OK;
+}
+
+// Writes C_k, D_k, S_{k-1} and the pending rules into scratch; also flags an
+// overflow of the reception not yet folded into C (sets si->overflow).
+int materialize(snp_sys* s, StateInfo* si) {
+  const int32_t q = s->q;
+  HIPCHK(launch_materialize(s->d, si->rbuf, si->sbuf, s->scratch, s->scratch + q,
+                            s->scratch + 2 * (size_t)q, s->scratch + 3 * (size_t)q, s->stream));
+  int32_t ov = 0;
+  HIPCHK(hipMemcpyAsync(&ov, &s->d.ctl->overflow, 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  si->overflow = si->overflow || ov != 0;
+  return SNP_OK;
+}
+
+int read_part(snp_sys* s, int part, int32_t* out) {
+  if (!s || !out) return fail(SNP_EINVAL, "null argument");
+  DevScope ds(s->dev);
+  StateInfo si;
+  TRY(query(s, &si));
+  TRY(materialize(s, &si));
+  HIPCHK(hipMemcpyAsync(out, s->scratch + (size_t)part * s->q, 4 * (size_t)s->q,
+                        hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return si.overflow ? fail(SNP_EOVERFLOW, "a spike count left the int32 range") : SNP_OK;
+}
+
+int capture_graph(snp_sys* s) {
+  s->graph_tried = true;
+  if (s->opts.flags & SNP_F_NO_GRAPH) return SNP_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return SNP_OK;  // this stream cannot be captured: launch directly
+  }
+  bool ok = true;
+  for (int32_t j = 0; j < s->chunk && ok; ++j) ok = launch_step(s->d, j, s->stream) == hipSuccess;
+  if (ok) ok = launch_advance(s->d.ctl, s->chunk, s->stream) == hipSuccess;
+  hipError_t e = hipStreamEndCapture(s->stream, &g);
+  if (!ok || e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return SNP_OK;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SNP_OK;
+  }
+  s->graph = ex;
+  return SNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void snp_opts_default(snp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->layout = SNP_LAYOUT_AUTO;
+  o->select = SNP_SELECT_FIRST;
+  o->semantics = SNP_SEM_STANDARD;
+  o->chunk = kDefaultChunk;
+  o->device = -1;
+  o->ring = kDefaultRing;
+}
+
+const char* snp_strerror(int st) {
+  switch (st) {
+    case SNP_OK: return "ok";
+    case SNP_EINVAL: return "invalid argument or invalid system";
+    case SNP_ENOMEM: return "out of memory";
+    case SNP_EDEVICE: return "HIP runtime error";
+    case SNP_EOVERFLOW: return "spike count overflow (int32)";
+    case SNP_EBUSY: return "handle is a member of a batch";
+    case SNP_ENOTSUP: return "outside the supported limits";
+    default: return "unknown status";
+  }
+}
+
+const char* snp_last_error(void) { return g_last_error.c_str(); }
+
+int snp_paper_sizes(int64_t q, int64_t m, int64_t z, int64_t* sparse, int64_t* ell,
+                    int64_t* compressed) {
+  if (q < 0 || m < 0 || z < 0) return fail(SNP_EINVAL, "negative size");
+  if (sparse) *sparse = m * q + 3 * m + 2 * q + 1;
+  if (ell) *ell = m * (2 * z + 5) + 2 * q + 1;
+  if (compressed) *compressed = q * (z + 3) + 4 * m + 1;
+  return SNP_OK;
+}
+
+int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layout, uint32_t flags,
+                  int64_t ring, int64_t* bytes) {
+  if (q < 1 || m < 0 || nsyn < 0 || zmax < 0 || !bytes) return fail(SNP_EINVAL, "bad shape");
+  if (layout == SNP_LAYOUT_AUTO) layout = SNP_LAYOUT_CSR_PULL;
+  if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
+  *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16);
+  return SNP_OK;
+}
+
+int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rules, int64_t nsyn,
+               const int32_t* syn_src, const int32_t* syn_dst, const snp_opts* opts_in,
+               snp_sys** out) {
+  if (!out) return fail(SNP_EINVAL, "null output handle");
+  *out = nullptr;
+  snp_opts o;
+  if (opts_in) o = *opts_in;
+  else snp_opts_default(&o);
+  if (q < 1) return fail(SNP_EINVAL, "q must be >= 1");
+  if (m < 0 || nsyn < 0) return fail(SNP_EINVAL, "negative count");
+  if (!spikes0 || (m > 0 && !rules) || (nsyn > 0 && (!syn_src || !syn_dst)))
+    return fail(SNP_EINVAL, "null array");
+  if (o.layout == SNP_LAYOUT_AUTO) o.layout = SNP_LAYOUT_CSR_PULL;
+  if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
+  if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
+  if (o.semantics != SNP_SEM_STANDARD && o.semantics != SNP_SEM_PAPER_KERNEL)
+    return fail(SNP_EINVAL, "bad semantics");
+  if (o.chunk <= 0) o.chunk = kDefaultChunk;
+  if (o.ring <= 0) o.ring = kDefaultRing;
+  if (o.ring < 4) o.ring = 4;
+  if (nsyn > 0x7FFFFFFELL) return fail(SNP_ENOTSUP, "more than 2^31-2 synapses");
+
+  // ---- validation (Sec. 2) ----
+  for (int32_t i = 0; i < q; ++i)
+    if (spikes0[i] < 0) return fail(SNP_EINVAL, "negative initial spikes");
+  int32_t pmax_all = 0;
+  for (int32_t r = 0; r < m; ++r) {
+    const snp_rule& x = rules[r];
+    if (x.neuron < 0 || x.neuron >= q) return fail(SNP_EINVAL, "rule neuron out of range");
+    if (x.base < 0 || x.period < 0 || x.c < 1 || x.p < 0 || x.d < 0)
+      return fail(SNP_EINVAL, "rule field out of range");
+    if (x.p > 0xFFFF || x.d > 0xFFFF) return fail(SNP_ENOTSUP, "p or d above 65535");
+    pmax_all = std::max(pmax_all, x.p);
+  }
+  for (int64_t e = 0; e < nsyn; ++e) {
+    if (syn_src[e] < 0 || syn_src[e] >= q || syn_dst[e] < 0 || syn_dst[e] >= q)
+      return fail(SNP_EINVAL, "synapse endpoint out of range");
+    if (syn_src[e] == syn_dst[e]) return fail(SNP_EINVAL, "reflexive synapse");
+  }
+
+  snp_sys* s = new (std::nothrow) snp_sys();
+  if (!s) return fail(SNP_ENOMEM, "host allocation failed");
+  s->opts = o;
+  s->q = q;
+  s->m = m;
+  s->nnz = nsyn;
+  s->layout = o.layout;
+  s->chunk = o.chunk;
+
+  auto bail = [&](int st) {
+    s->release();
+    delete s;
+    return st;
+  };
+
+  // ---- device and stream ----
+  if (o.device >= 0) {
+    s->dev = o.device;
+  } else if (hipGetDevice(&s->dev) != hipSuccess) {
+    return bail(fail(SNP_EDEVICE, "no HIP device"));
+  }
+  DevScope ds(s->dev);
+  if (!ds.ok) return bail(fail(SNP_EDEVICE, "cannot select device"));
+  if (o.stream) {
+    s->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(SNP_EDEVICE, "stream creation failed"));
+    s->own_stream = true;
+  }
+
+  // ---- neuron-rule map: rules in neuron order, stable by caller id ----
+  std::vector<int32_t>& rs = s->h_rs;
+  rs.assign((size_t)q + 1, 0);
+  for (int32_t r = 0; r < m; ++r) rs[(size_t)rules[r].neuron + 1]++;
+  int32_t maxr = 0;
+  for (int32_t i = 0; i < q; ++i) {
+    maxr = std::max(maxr, rs[(size_t)i + 1]);
+    rs[(size_t)i + 1] += rs[i];
+  }
+  if (maxr > 0xFFFE) return bail(fail(SNP_ENOTSUP, "more than 65534 rules on one neuron"));
+  s->h_rid.assign((size_t)std::max(m, 1), 0);
+  s->h_slot.assign((size_t)std::max(m, 1), 0);
+  std::vector<RuleRec> rec((size_t)std::max(m, 1));
+  std::vector<int32_t> pmax((size_t)q, 0);
+  {
+    std::vector<int32_t> fill(rs.begin(), rs.end() - 1);
+    for (int32_t r = 0; r < m; ++r) {
+      const snp_rule& x = rules[r];
+      const int32_t slot = fill[x.neuron]++;
+      s->h_rid[slot] = r;
+      s->h_slot[r] = slot;
+      RuleRec& R = rec[slot];
+      if (x.period == 0) {
+        R.period = 0;
+        R.lo = x.base >= x.c ? x.base : -1;
+      } else {
+        const int64_t lo0 = std::max(x.base, x.c);
+        const int64_t steps = (lo0 - x.base + x.period - 1) / x.period;
+        const int64_t lo = (int64_t)x.base + steps * x.period;
+        if (lo > 0x7FFFFFFFLL) {
+          R.period = 0;
+          R.lo = -1;
+        } else {
+          R.period = x.period;
+          R.lo = (int32_t)lo;
+        }
+      }
+      R.c = x.c;
+      R.pd = (uint32_t)x.p | ((uint32_t)x.d << 16);
+      pmax[x.neuron] = std::max(pmax[x.neuron], x.p);
+    }
+  }
+
+  // ---- synapses: out-lists sorted by target, in-lists sorted by source ----
+  std::vector<int32_t>& op = s->h_out_ptr;
+  std::vector<int32_t>& oc = s->h_out_col;
+  op.assign((size_t)q + 1, 0);
+  for (int64_t e = 0; e < nsyn; ++e) op[(size_t)syn_src[e] + 1]++;
+  int32_t z = 0;
+  for (int32_t i = 0; i < q; ++i) {
+    z = std::max(z, op[(size_t)i + 1]);
+    op[(size_t)i + 1] += op[i];
+  }
+  oc.assign((size_t)std::max<int64_t>(nsyn, 1), 0);
+  {
+    std::vector<int32_t> fill(op.begin(), op.end() - 1);
+    for (int64_t e = 0; e < nsyn; ++e) oc[fill[syn_src[e]]++] = syn_dst[e];
+  }
+  for (int32_t i = 0; i < q; ++i) {
+    auto b = oc.begin() + op[i], en = oc.begin() + op[(size_t)i + 1];
+    std::sort(b, en);
+    if (std::adjacent_find(b, en) != en) return bail(fail(SNP_EINVAL, "repeated synapse"));
+  }
+  s->z = z;
+  {
+    // a neuron must not be able to receive 2^31 spikes or more in one step
+    std::vector<int64_t> inmax((size_t)q, 0);
+    for (int32_t i = 0; i < q; ++i)
+      if (pmax[i] > 0)
+        for (int32_t e = op[i]; e < op[(size_t)i + 1]; ++e) inmax[oc[e]] += pmax[i];
+    for (int32_t t = 0; t < q; ++t)
+      if (inmax[t] > 0x7FFFFFFFLL) return bail(fail(SNP_ENOTSUP, "in-neighbours can send 2^31 spikes"));
+  }
+  const bool pull = o.layout == SNP_LAYOUT_CSR_PULL;
+  if (pull) {
+    std::vector<int32_t>& ip = s->h_in_ptr;
+    std::vector<int32_t>& is = s->h_in_src;
+    ip.assign((size_t)q + 1, 0);
+    for (int64_t e = 0; e < nsyn; ++e) ip[(size_t)oc[e] + 1]++;
+    for (int32_t i = 0; i < q; ++i) ip[(size_t)i + 1] += ip[i];
+    is.assign((size_t)std::max<int64_t>(nsyn, 1), 0);
+    std::vector<int32_t> fill(ip.begin(), ip.end() - 1);
+    for (int32_t i = 0; i < q; ++i)
+      for (int32_t e = op[i]; e < op[(size_t)i + 1]; ++e) is[fill[oc[e]]++] = i;
+  }
+
+  // ---- device arrays ----
+  SysDev& d = s->d;
+  d.q = q;
+  d.m = m;
+  d.z = z;
+  d.layout = o.layout;
+  d.sel = o.select;
+  d.sem = o.semantics;
+  d.flags = o.flags & (SNP_F_DIGEST | SNP_F_COUNTERS);
+  d.seed = o.seed;
+  d.ring = o.ring;
+  d.emit_w = emit_width(pmax_all);
+  d.pull_chunk = pull_chunk_sources(d.emit_w);
+
+  int st;
+  if ((st = upload(s, &d.C, spikes0, (size_t)q)) != SNP_OK) return bail(st);
+  if ((st = alloc_fill(s, (void**)&d.meta, 4 * (size_t)q, 0)) != SNP_OK) return bail(st);
+  if ((st = alloc_fill(s, (void**)&d.pend, 4 * (size_t)q, 0xFF)) != SNP_OK) return bail(st);
+  for (int b = 0; b < 2; ++b)
+    if ((st = alloc_fill(s, (void**)&d.S16[b], 2 * (size_t)q, 0xFF)) != SNP_OK) return bail(st);
+  {
+    int32_t* p;
+    if ((st = upload(s, &p, rs.data(), rs.size())) != SNP_OK) return bail(st);
+    d.rs = p;
+    RuleRec* rp;
+    if ((st = upload(s, &rp, rec.data(), (size_t)m)) != SNP_OK) return bail(st);
+    d.rules = rp;
+    if ((st = upload(s, &p, s->h_rid.data(), (size_t)m)) != SNP_OK) return bail(st);
+    d.rid = p;
+    if ((st = upload(s, &s->slot_of, s->h_slot.data(), (size_t)m)) != SNP_OK) return bail(st);
+  }
+  if ((st = alloc_fill(s, (void**)&d.ctl, sizeof(Ctl), 0)) != SNP_OK) return bail(st);
+  if ((st = alloc_fill(s, (void**)&s->scratch, 16 * (size_t)q, 0)) != SNP_OK) return bail(st);
+  if ((st = alloc_fill(s, (void**)&s->dig_tmp, 16, 0)) != SNP_OK) return bail(st);
+  if (d.flags & F_DIGEST)
+    if ((st = alloc_fill(s, (void**)&d.digests, 8 * (size_t)o.ring, 0)) != SNP_OK) return bail(st);
+  if (d.flags & F_COUNTERS)
+    if ((st = alloc_fill(s, (void**)&d.counters, 8 * NCOUNT * (size_t)(o.ring + 1), 0)) != SNP_OK)
+      return bail(st);
+
+  if (pull) {
+    int32_t* p;
+    if ((st = upload(s, &p, s->h_in_ptr.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
+    d.in_ptr = p;
+    if ((st = upload(s, &p, s->h_in_src.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
+    d.in_src = p;
+    const size_t tiles = ((size_t)q + pull_tile() - 1) / pull_tile();
+    const size_t words = tiles * (size_t)pull_tile() * d.emit_w / 32;
+    for (int b = 0; b < 2; ++b)
+      if ((st = alloc_fill(s, (void**)&d.emit[b], 4 * words, 0)) != SNP_OK) return bail(st);
+    if (d.flags & F_COUNTERS) {
+      std::vector<int32_t> deg((size_t)q);
+      for (int32_t i = 0; i < q; ++i) deg[i] = op[(size_t)i + 1] - op[i];
+      if ((st = upload(s, &p, deg.data(), (size_t)q)) != SNP_OK) return bail(st);
+      d.out_deg = p;
+    }
+  } else {
+    for (int b = 0; b < 2; ++b)
+      if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return bail(st);
+    int32_t* p;
+    if ((st = upload(s, &p, op.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
+    d.out_ptr = p;
+    if ((st = upload(s, &p, oc.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
+    d.out_col = p;
+    if (o.layout == SNP_LAYOUT_OPTIMIZED) {
+      int32_t* sy = (int32_t*)s->dalloc(4 * (size_t)z * q);
+      if (!sy) return bail(fail(SNP_ENOMEM, "Sy does not fit in device memory"));
+      d.sy = sy;
+      if (hipSuccess != launch_build_sy(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy"));
+    } else if (o.layout == SNP_LAYOUT_ELL) {
+      int2* ell = (int2*)s->dalloc(8 * (size_t)(z + 1) * (size_t)std::max(m, 1));
+      if (!ell) return bail(fail(SNP_ENOMEM, "ELL does not fit in device memory"));
+      d.ell = ell;
+      if (hipSuccess != launch_build_ell(d, ell, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
+    }
+  }
+  if (hipStreamSynchronize(s->stream) != hipSuccess)
+    return bail(fail(SNP_EDEVICE, std::string("create: ") + hipGetErrorString(hipGetLastError())));
+  *out = s;
+  return SNP_OK;
+}
+
+int snp_step(snp_sys* s, int64_t k) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
+  if (k <= 0) return SNP_OK;
+  DevScope ds(s->dev);
+  if (!s->graph_tried && k >= s->chunk) {
+    int st = capture_graph(s);
+    if (st != SNP_OK) return st;
+  }
+  while (k > 0) {
+    if (s->graph && k >= s->chunk) {
+      HIPCHK(hipGraphLaunch(s->graph, s->stream));
+      k -= s->chunk;
+      continue;
+    }
+    const int32_t n = (int32_t)std::min<int64_t>(k, s->chunk);
+    for (int32_t j = 0; j < n; ++j) HIPCHK(launch_step(s->d, j, s->stream));
+    HIPCHK(launch_advance(s->d.ctl, n, s->stream));
+    k -= n;
+  }
+  return SNP_OK;
+}
+
+int snp_steps_done(snp_sys* s, int64_t* steps, int32_t* halted) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  DevScope ds(s->dev);
+  StateInfo si;
+  TRY(query(s, &si));
+  TRY(materialize(s, &si));
+  if (steps) *steps = si.steps;
+  if (halted) {
+    if (si.halted_seen) {
+      *halted = 1;
+    } else {
+      // evaluate the current state: test every open neuron of the materialized state
+      int32_t act = 0;
+      HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 8, s->stream));
+      HIPCHK(launch_activity(s->d, s->scratch, s->scratch + s->q, (int32_t*)s->dig_tmp, s->stream));
+      HIPCHK(hipMemcpyAsync(&act, s->dig_tmp, 4, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+      *halted = act ? 0 : 1;
+    }
+  }
+  return si.overflow ? fail(SNP_EOVERFLOW, "a spike count left the int32 range") : SNP_OK;
+}
+
+int snp_read_config(snp_sys* s, int32_t* out) { return read_part(s, 0, out); }
+int snp_read_delays(snp_sys* s, int32_t* out) { return read_part(s, 1, out); }
+int snp_read_spiking(snp_sys* s, int32_t* out) { return read_part(s, 2, out); }
+int snp_read_pending(snp_sys* s, int32_t* out) { return read_part(s, 3, out); }
+
+int snp_digest(snp_sys* s, uint64_t* out) {
+  if (!s || !out) return fail(SNP_EINVAL, "null argument");
+  DevScope ds(s->dev);
+  StateInfo si;
+  TRY(query(s, &si));
+  TRY(materialize(s, &si));
+  HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 8, s->stream));
+  HIPCHK(launch_digest(s->scratch, s->scratch + s->q, s->scratch + 2 * (size_t)s->q, s->q,
+                       s->dig_tmp, s->stream));
+  HIPCHK(hipMemcpyAsync(out, s->dig_tmp, 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return SNP_OK;
+}
+
+int snp_read_digests(snp_sys* s, uint64_t* out, int64_t first, int64_t count) {
+  if (!s || (!out && count > 0) || first < 0 || count < 0) return fail(SNP_EINVAL, "bad argument");
+  if (!(s->d.flags & F_DIGEST)) return fail(SNP_EINVAL, "created without SNP_F_DIGEST");
+  DevScope ds(s->dev);
+  StateInfo si;
+  TRY(query(s, &si));
+  if (first + count > si.steps) return fail(SNP_EINVAL, "digest of a state not reached");
+  // digest of the state after step t+1 is written by step kernel t+1
+  const int64_t lastk = si.kx - 1;  // last kernel that ran
+  const int64_t lo = std::max<int64_t>(0, lastk - s->d.ring + 1);
+  std::vector<uint64_t> ring((size_t)s->d.ring);
+  HIPCHK(hipMemcpy(ring.data(), s->d.digests, 8 * (size_t)s->d.ring, hipMemcpyDeviceToHost));
+  for (int64_t t = first; t < first + count; ++t) {
+    if (t + 1 <= lastk) {
+      if (t < lo) return fail(SNP_EINVAL, "digest no longer in the ring");
+      out[t - first] = ring[(size_t)(t % s->d.ring)];
+    } else {
+      uint64_t v;
+      TRY(snp_digest(s, &v));  // the current state
+      out[t - first] = v;
+    }
+  }
+  return SNP_OK;
+}
+
+int snp_read_counters(snp_sys* s, snp_counters* out, int64_t first, int64_t count) {
+  if (!s || (!out && count > 0) || first < 0 || count < 0) return fail(SNP_EINVAL, "bad argument");
+  if (!(s->d.flags & F_COUNTERS)) return fail(SNP_EINVAL, "created without SNP_F_COUNTERS");
+  DevScope ds(s->dev);
+  StateInfo si;
+  TRY(query(s, &si));
+  if (first + count > si.steps) return fail(SNP_EINVAL, "step not executed");
+  const int64_t R = s->d.ring;
+  if (count > 0 && first < si.kx - R + 1) return fail(SNP_EINVAL, "counters no longer in the ring");
+  std::vector<unsigned long long> ring((size_t)R * NCOUNT);
+  HIPCHK(hipMemcpy(ring.data(), s->d.counters, 8 * (size_t)R * NCOUNT, hipMemcpyDeviceToHost));
+  unsigned long long tail[2] = {0, 0};
+  if (first + count == si.steps && si.steps == si.kx) {
+    // the reception of the last executed step is still pending: count it now
+    HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 16, s->stream));
+    HIPCHK(launch_recv_counts(s->d, si.rbuf, s->dig_tmp, s->stream));
+    HIPCHK(hipMemcpyAsync(tail, s->dig_tmp, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
+  for (int64_t t = first; t < first + count; ++t) {
+    const unsigned long long* c = &ring[(size_t)(t % R) * NCOUNT];
+    int64_t v[NCOUNT];
+    for (int x = 0; x < NCOUNT; ++x) v[x] = (int64_t)c[x];
+    if (t == si.steps - 1 && si.steps == si.kx) {
+      v[6] = (int64_t)tail[0];  // spikes_lost
+      v[7] = (int64_t)tail[1];  // receiving
+    }
+    snp_counters& o = out[t - first];
+    o.open_neurons = v[0];
+    o.rules_of_open = v[1];
+    o.selecting = v[2];
+    o.emitting = v[3];
+    o.emit_edges = v[4];
+    o.spikes_sent = v[5];
+    o.spikes_lost = v[6];
+    o.receiving = v[7];
+    o.reopening = v[8];
+  }
+  return SNP_OK;
+}
+
+int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_t* P,
+                    const int32_t* S, int64_t k) {
+  if (!s || !C || !D || k < 0 || k > 0x7FFFFFFFLL) return fail(SNP_EINVAL, "bad argument");
+  if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
+  const int32_t q = s->q;
+  for (int32_t i = 0; i < q; ++i) {
+    if (C[i] < 0 || D[i] < 0) return fail(SNP_EINVAL, "negative count or delay");
+    const bool owns_p = P && P[i] >= 0;
+    if (P && P[i] >= s->m) return fail(SNP_EINVAL, "pending rule out of range");
+    if (owns_p) {
+      const int32_t sl = s->h_slot[P[i]];
+      if (sl < s->h_rs[i] || sl >= s->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "pending rule of another neuron");
+    }
+    if (S && S[i] >= 0) {
+      if (S[i] >= s->m) return fail(SNP_EINVAL, "spiking rule out of range");
+      const int32_t sl = s->h_slot[S[i]];
+      if (sl < s->h_rs[i] || sl >= s->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "spiking rule of another neuron");
+    }
+    if (s->opts.semantics == SNP_SEM_STANDARD && D[i] > 0 && !owns_p)
+      return fail(SNP_EINVAL, "closed neuron without pending rule");
+  }
+  DevScope ds(s->dev);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  int32_t* tmp = s->scratch;  // [4][q]: C, D, P, S
+  HIPCHK(hipMemcpyAsync(tmp, C, 4 * (size_t)q, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(tmp + q, D, 4 * (size_t)q, hipMemcpyHostToDevice, s->stream));
+  if (P) HIPCHK(hipMemcpyAsync(tmp + 2 * (size_t)q, P, 4 * (size_t)q, hipMemcpyHostToDevice, s->stream));
+  if (S) HIPCHK(hipMemcpyAsync(tmp + 3 * (size_t)q, S, 4 * (size_t)q, hipMemcpyHostToDevice, s->stream));
+  const int32_t sbuf = k >= 1 ? (int32_t)((k - 1) & 1) : -1;
+  HIPCHK(launch_restore(s->d, sbuf, tmp, tmp + q, P ? tmp + 2 * (size_t)q : nullptr,
+                        S ? tmp + 3 * (size_t)q : nullptr, s->slot_of, s->stream));
+  // nothing is in flight towards the restored state
+  if (s->layout == SNP_LAYOUT_CSR_PULL) {
+    const size_t tiles = ((size_t)q + pull_tile() - 1) / pull_tile();
+    const size_t words = tiles * (size_t)pull_tile() * s->d.emit_w / 32;
+    for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.emit[b], 0, 4 * words, s->stream));
+  } else {
+    for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.delta[b], 0, 4 * (size_t)q, s->stream));
+  }
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.k_base = k;
+  c.k_exec = k;
+  if (k >= 1) c.active[(k - 1) % 3] = 1;
+  HIPCHK(hipMemcpyAsync(s->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  if (s->d.flags & F_COUNTERS)
+    HIPCHK(hipMemsetAsync(s->d.counters, 0, 8 * NCOUNT * (size_t)(s->d.ring + 1), s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return SNP_OK;
+}
+
+int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int64_t* needed) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  DevScope ds(s->dev);
+  const int32_t q = s->q, m = s->m, z = s->z;
+  int64_t need = 0;
+  if (which == SNP_LAYOUT_OPTIMIZED) need = (int64_t)z * q;
+  else if (which == SNP_LAYOUT_ELL) need = 2LL * (z + 1) * m;
+  else if (which == SNP_LAYOUT_CSR_PUSH) need = (int64_t)q + 1 + s->nnz;
+  else if (which == SNP_LAYOUT_CSR_PULL) need = (int64_t)q + 1 + s->nnz;
+  else return fail(SNP_EINVAL, "bad layout id");
+  if (needed) *needed = need;
+  if (!out) return SNP_OK;
+  if (count < need) return fail(SNP_EINVAL, "buffer too small");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (which == SNP_LAYOUT_OPTIMIZED) {
+    if (!s->d.sy) return fail(SNP_EINVAL, "handle does not use the Optimized layout");
+    HIPCHK(hipMemcpy(out, s->d.sy, 4 * (size_t)need, hipMemcpyDeviceToHost));
+  } else if (which == SNP_LAYOUT_ELL) {
+    if (!s->d.ell) return fail(SNP_EINVAL, "handle does not use the ELL layout");
+    std::vector<int32_t> tmp((size_t)need);
+    HIPCHK(hipMemcpy(tmp.data(), s->d.ell, 4 * (size_t)need, hipMemcpyDeviceToHost));
+    for (int64_t row = 0; row <= z; ++row)
+      for (int32_t sl = 0; sl < m; ++sl) {
+        const int64_t src = (row * m + sl) * 2, dst = (row * m + s->h_rid[sl]) * 2;
+        out[dst] = tmp[(size_t)src];
+        out[dst + 1] = tmp[(size_t)src + 1];
+      }
+  } else if (which == SNP_LAYOUT_CSR_PUSH) {
+    if (!s->d.out_ptr) return fail(SNP_EINVAL, "handle keeps no out-neighbour lists");
+    HIPCHK(hipMemcpy(out, s->d.out_ptr, 4 * ((size_t)q + 1), hipMemcpyDeviceToHost));
+    if (s->nnz) HIPCHK(hipMemcpy(out + q + 1, s->d.out_col, 4 * (size_t)s->nnz, hipMemcpyDeviceToHost));
+  } else {
+    if (!s->d.in_ptr) return fail(SNP_EINVAL, "handle keeps no in-neighbour lists");
+    HIPCHK(hipMemcpy(out, s->d.in_ptr, 4 * ((size_t)q + 1), hipMemcpyDeviceToHost));
+    if (s->nnz) HIPCHK(hipMemcpy(out + q + 1, s->d.in_src, 4 * (size_t)s->nnz, hipMemcpyDeviceToHost));
+  }
+  return SNP_OK;
+}
+
+int snp_info(snp_sys* s, int32_t* q, int32_t* m, int64_t* nsyn, int32_t* zmax, int32_t* layout) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  if (q) *q = s->q;
+  if (m) *m = s->m;
+  if (nsyn) *nsyn = s->nnz;
+  if (zmax) *zmax = s->z;
+  if (layout) *layout = s->layout;
+  return SNP_OK;
+}
+
+void* snp_stream(snp_sys* s) { return s ? (void*)s->stream : nullptr; }
+
+int snp_destroy(snp_sys* s) {
+  if (!s) return SNP_OK;
+  if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
+  {
+    DevScope ds(s->dev);
+    s->release();
+  }
+  delete s;
+  return SNP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal device-side structures of the SNP simulator (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snp {
+
+enum : int32_t { L_OPT = 1, L_ELL = 2, L_CSR_PUSH = 3, L_CSR_PULL = 4 };
+enum : int32_t { SEL_FIRST = 0, SEL_HASH = 1 };
+enum : int32_t { SEM_STANDARD = 0, SEM_PAPER = 1 };
+enum : uint32_t { F_DIGEST = 1u, F_COUNTERS = 2u };
+
+// meta word of a neuron: delay counter D (bits 0..30) and, in bit 31, whether
+// the neuron receives the spikes sent at the step that produced this word.
+constexpr uint32_t META_RECV = 0x80000000u;
+constexpr uint32_t META_D = 0x7FFFFFFFu;
+constexpr uint16_t S_NONE = 0xFFFFu;
+constexpr int NCOUNT = 9;  // fields of snp_counters
+
+// One rule of the rule vector RV in neuron order (16 bytes).
+//   Applicability of E = a^base (a^period)* together with n >= c is
+//   rewritten as a single test on (lo, period):
+//     period == 0 : n == lo            (lo = base, or -1 if base < c: never)
+//     period >= 1 : n >= lo and (n - lo) % period == 0, where lo is the
+//                   smallest count >= max(base, c) in the expression's set.
+struct RuleRec {
+  int32_t lo;
+  int32_t period;
+  int32_t c;
+  uint32_t pd;  // p | d << 16
+};
+
+// Control block of one system, in device memory.
+struct Ctl {
+  int64_t k_base;     // system-local index of launch 0 of the current run of launches
+  int64_t k_exec;     // index + 1 of the last step kernel whose body ran
+  int64_t halt_step;  // executed steps when the halt was seen
+  int32_t halted;     // sticky: a kernel found the previous state halted
+  int32_t overflow;   // sticky: a finalized count left the int32 range
+  int32_t active[4];  // active[k % 3] != 0 iff state k had an active neuron
+  int32_t pad[6];
+};
+
+struct SysDev {
+  int32_t q, m, z;           // neurons, rules, MaxOutDegree
+  int32_t layout, sel, sem;
+  uint32_t flags;
+  int32_t emit_w;            // pull: bits per emitted value
+  uint64_t seed;             // HASH key (mixed once more on the device)
+  // state
+  int32_t* C;                // C_k minus the consumption of the last step
+  uint32_t* meta;            // D and the reception flag
+  int32_t* pend;             // rule slot waiting to send (STANDARD, D > 0)
+  uint16_t* S16[2];          // local index of the rule selected at step k (k & 1)
+  // rule vector, neuron-rule map
+  const int32_t* rs;         // [q+1] rules of neuron i: slots rs[i] .. rs[i+1]-1
+  const RuleRec* rules;      // [m] in slot order
+  const int32_t* rid;        // [m] caller id of each slot
+  // push representations
+  int32_t* delta[2];         // spikes received at step k, by k & 1
+  const int32_t* sy;         // OPTIMIZED: [z][q] row-major, -1 = null
+  const int2* ell;           // ELL: [z+1][m] row-major (neuron, value), (-1, 0) = null
+  const int32_t* out_ptr;    // CSR_PUSH: [q+1]
+  const int32_t* out_col;    // CSR_PUSH: [nnz]
+  const int32_t* out_deg;    // counters only: [q]
+  // pull representation
+  const int32_t* in_ptr;     // [q+1]
+  const int32_t* in_src;     // [nnz], each list in increasing source id
+  uint32_t* emit[2];         // packed emit_w-bit values by k & 1
+  int32_t pull_chunk;        // sources per LDS chunk
+  // bookkeeping
+  Ctl* ctl;
+  uint64_t* digests;         // ring [ring]
+  unsigned long long* counters;  // ring [ring][NCOUNT]
+  int64_t ring;
+};
+
+// Host-side launchers (defined in snp_kernels.hip).
+hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_advance(Ctl* ctl, int32_t n, hipStream_t st);
+hipError_t launch_materialize(const SysDev& s, int32_t rbuf, int32_t sbuf, int32_t* outC,
+                              int32_t* outD, int32_t* outS, int32_t* outP, hipStream_t st);
+hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, int32_t q,
+                         unsigned long long* out, hipStream_t st);
+hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st);
+hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st);
+hipError_t launch_restore(const SysDev& s, int32_t sbuf, const int32_t* C, const int32_t* D,
+                          const int32_t* P, const int32_t* S, const int32_t* slot_of_rule,
+                          hipStream_t st);
+hipError_t launch_activity(const SysDev& s, const int32_t* C, const int32_t* D, int32_t* out,
+                           hipStream_t st);
+hipError_t launch_recv_counts(const SysDev& s, int32_t rbuf, unsigned long long* out2,
+                              hipStream_t st);
+int pull_threads();
+int pull_tile();
+size_t pull_lds_bytes(const SysDev& s);
+
+}  // namespace snp

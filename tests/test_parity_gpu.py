@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer state, so the bar is bit-exact: C, D, S and the pending rule at every
+step on small systems (several pull tiles, ragged tails, every layout, both
+delay readings, both choice modes), digests of every step on larger ones.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2408_04343_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ["csr_pull", "optimized", "ell", "csr_push"]
+SEMS = [("standard", orc.SEM_STANDARD), ("paper_kernel", orc.SEM_PAPER_KERNEL)]
+
+
+@pytest.fixture(scope="module")
+def binding():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_2408_04343_amd import binding as b
+    return b
+
+
+def oracle_of(spec, sem, sel=None, seed=None):
+    return orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, sem,
+                            spec.select if sel is None else sel, spec.seed if seed is None else seed)
+
+
+def gpu_of(binding, spec, layout, sem_name, **kw):
+    return binding.System.from_spec(spec, layout=layout, semantics=sem_name, **kw)
+
+
+def compare_every_step(binding, spec, layout, sem_name, sem, steps, **kw):
+    ref_sys = oracle_of(spec, sem)
+    ref = ref_sys.step_record(steps)
+    g = gpu_of(binding, spec, layout, sem_name, **kw)
+    pend_ref = oracle_of(spec, sem)
+    for t in range(ref["steps"]):
+        g.step(1)
+        pend_ref.step(1)
+        C, D, S, P = g.read_config(), g.read_delays(), g.read_spiking(), g.read_pending()
+        assert np.array_equal(C, ref["C"][t]), (spec.name, layout, sem_name, t, "C")
+        assert np.array_equal(D, ref["D"][t]), (spec.name, layout, sem_name, t, "D")
+        assert np.array_equal(S, ref["S"][t]), (spec.name, layout, sem_name, t, "S")
+        assert np.array_equal(P, pend_ref.read()["pend"]), (spec.name, layout, sem_name, t, "pend")
+    steps_done, halted = g.steps_done()
+    assert steps_done == ref["steps"]
+    assert halted == ref_sys.halted
+    g.close()
+    return ref["steps"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("sem_name,sem", SEMS)
+def test_config1_every_step(binding, layout, sem_name, sem):
+    spec = wl.config1()
+    compare_every_step(binding, spec, layout, sem_name, sem, 100)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("q", [1, 7, 2047, 2048, 2049, 6001])
+def test_hash_ragged_sizes_every_step(binding, layout, q):
+    spec = wl.small_random(q, q, max_deg=min(9, q - 1) if q > 1 else 0, max_rules=4, dmax=3,
+                           c0max=8, select=wl.SELECT_HASH, steps=25)
+    for sem_name, sem in SEMS:
+        compare_every_step(binding, spec, layout, sem_name, sem, 25)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_hand_trace_h1(binding, layout):
+    rules = np.array([(0, 1, 0, 1, 1, 2), (1, 1, 0, 1, 1, 0)], np.int32)
+    spec = wl.SnpSpec("h1", 3, np.array([1, 1, 0], np.int32), rules,
+                      np.array([0, 1, 1], np.int32), np.array([1, 0, 2], np.int32))
+    assert compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 12) == 12
+    assert compare_every_step(binding, spec, layout, "paper_kernel", orc.SEM_PAPER_KERNEL, 12) == 6
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("sel,seed", [("first", 0), ("hash", 1)])
+def test_hand_trace_h2(binding, layout, sel, seed):
+    rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
+    g = binding.System(1, [4], rules, [], [], layout=layout, select=sel, seed=seed)
+    g.step(10)
+    assert g.steps_done() == (2, True)
+    assert g.read_config().tolist() == [0]
+    assert g.read_spiking().tolist() == [1 if sel == "first" else 0]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_sort_family_closed_form(binding, layout):
+    rng = np.random.default_rng(11)
+    for n in (3, 17, 100):
+        v = rng.integers(1, 60, size=n).tolist() if n != 100 else list(range(100, 0, -1))
+        spec = wl.sort_system(v)
+        g = binding.System.from_spec(spec, layout=layout)
+        g.step(10_000)
+        steps, halted = g.steps_done()
+        assert (steps, halted) == (max(v) + 1, True)
+        C = g.read_config()
+        assert C[2 * n:].tolist() == sorted(v)
+        assert not C[:2 * n].any()
+        g.close()
+
+
+def test_layouts_built_on_device_match_tables(binding):
+    from tests._golden import int_matrix
+    spec = wl.sort_system([3, 1, 2])
+    g = binding.System.from_spec(spec, layout="optimized")
+    sy = g.read_layout("optimized").reshape(3, 9)
+    assert sy.tolist() == int_matrix("table3_sort3_sy.txt")
+    g = binding.System.from_spec(spec, layout="ell")
+    ell = g.read_layout("ell").reshape(4, 12, 2)
+    nid, val = oracle_of(spec, orc.SEM_STANDARD).ell()   # pinned to Table 2
+    assert np.array_equal(ell[..., 0], nid) and np.array_equal(ell[..., 1], val)
+
+
+def test_device_layouts_match_oracle_on_random_system(binding):
+    spec = wl.small_random(5, 3000, max_deg=12, max_rules=4)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    g = binding.System.from_spec(spec, layout="optimized")
+    assert np.array_equal(g.read_layout("optimized").reshape(o.sy().shape), o.sy())
+    g = binding.System.from_spec(spec, layout="ell")
+    nid, val = o.ell()
+    ell = g.read_layout("ell").reshape(nid.shape[0], nid.shape[1], 2)
+    assert np.array_equal(ell[..., 0], nid) and np.array_equal(ell[..., 1], val)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_graph_chunks_digests(binding, layout):
+    spec = wl.small_random(21, 9000, max_deg=16, max_rules=4, dmax=3, c0max=8,
+                           select=wl.SELECT_HASH)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(300, want_state=False)
+    g = binding.System.from_spec(spec, layout=layout, digest=True, chunk=64)
+    g.step(130)       # two captured chunks + direct launches
+    g.step(170)
+    n = ref["steps"]
+    assert g.steps_done()[0] == n
+    assert np.array_equal(g.read_digests(0, n), ref["digests"])
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_counters_match_oracle(binding, layout):
+    spec = wl.small_random(8, 5000, max_deg=10, max_rules=4, dmax=3, c0max=8)
+    for sem_name, sem in SEMS:
+        ref = oracle_of(spec, sem).step_record(40, want_state=False)
+        g = binding.System.from_spec(spec, layout=layout, semantics=sem_name, counters=True)
+        g.step(40)
+        got = g.read_counters(0, ref["steps"])
+        assert got == ref["counters"], (layout, sem_name)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_split_and_resume_equal_uninterrupted(binding, layout):
+    spec = wl.small_random(31, 4000, max_deg=8, max_rules=3, dmax=3, select=wl.SELECT_HASH)
+    a = binding.System.from_spec(spec, layout=layout)
+    a.step(37)
+    a.step(1)
+    a.step(62)
+    b = binding.System.from_spec(spec, layout=layout)
+    b.step(40)
+    snap = (b.read_config(), b.read_delays(), b.read_pending(), b.read_spiking())
+    c = binding.System.from_spec(spec, layout=layout)
+    c.write_state(*snap, k=40)
+    c.step(60)
+    ref = oracle_of(spec, orc.SEM_STANDARD)
+    ref.step(100)
+    r = ref.read()
+    for sysg in (a, c):
+        assert sysg.steps_done()[0] == 100
+        assert np.array_equal(sysg.read_config(), r["C"])
+        assert np.array_equal(sysg.read_delays(), r["D"])
+        assert np.array_equal(sysg.read_spiking(), r["S"])
+        assert np.array_equal(sysg.read_pending(), r["pend"])
+
+
+@pytest.mark.parametrize("W,pmax", [(2, 3), (4, 15), (8, 200), (16, 60000)])
+def test_pull_emit_widths(binding, W, pmax):
+    rng = np.random.default_rng(W)
+    spec = wl.small_random(40 + W, 5000, max_deg=6, max_rules=3, dmax=2, c0max=8)
+    spec.rules[:, 4] = rng.integers(0, pmax + 1, size=spec.m)
+    spec.rules[0, 4] = pmax
+    compare_every_step(binding, spec, "csr_pull", "standard", orc.SEM_STANDARD, 15)
+
+
+def test_pull_several_lds_chunks(binding):
+    # 600k neurons with p <= 2: the emitted values span several LDS chunks
+    spec = wl.config2(q=600_000, steps=20)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(20, want_state=False)
+    for layout in ("csr_pull", "csr_push"):
+        g = binding.System.from_spec(spec, layout=layout, digest=True)
+        g.step(20)
+        assert np.array_equal(g.read_digests(0, 20), ref["digests"]), layout
+        g.close()
+
+
+def test_overflow_reported(binding):
+    big = 2 ** 31 - 2
+    for layout in LAYOUTS:
+        g = binding.System(2, [1, big], [(0, 1, 0, 1, 5, 0)], [0], [1], layout=layout)
+        g.step(1)
+        with pytest.raises(binding.SnpError) as ei:
+            g.steps_done()
+        assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("bad", [dict(src=[0, 0], dst=[1, 1])])
+def test_repeated_synapse_rejected(binding, bad):
+    with pytest.raises(binding.SnpError) as ei:
+        binding.System(2, [1, 1], [(0, 1, 0, 1, 1, 0)], bad["src"], bad["dst"])
+    assert ei.value.status == -1
+
+
+def test_torch_and_hip_memory_agree(binding):
+    spec = wl.small_random(77, 3000, max_deg=8, select=wl.SELECT_HASH)
+    a = binding.System.from_spec(spec, memory="torch")
+    b = binding.System.from_spec(spec, memory="hip")
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.read_config(), b.read_config())
+    assert a.digest() == b.digest()
+
+
+def test_digest_of_current_state(binding):
+    spec = wl.config1()
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    g = binding.System.from_spec(spec)
+    for n in (0, 1, 5, 50):
+        o.step(n)
+        g.step(n)
+        assert g.digest() == o.digest()
