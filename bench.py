@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the SNP-with-delays step on one MI355X.
+
+Workload (the headline): 1,048,576 neurons, out-degree min(Poisson(16), 64)
+with uniformly random distinct targets, 1-4 rules per neuron (E = a^k or
+a^k(a^j)*, c = k, p in 1..2, d in 0..3), initial spikes U{0..8}, lowest-index
+rule fires, 1,000 steps; seeded synthetic input.  A "step" is one transition
+of the whole system (one fused step kernel launch).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "neuron-updates/s + HBM GB/s (% peak), batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("config2-large: 1,048,576 neurons, Poisson(16) out-degree (cap 64), 1-4 rules/neuron, "
+            "delays 0..3, initial spikes U{0..8}, lowest-index rule, 1,000 steps")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes of one step, from the exact per-step work counters.
+# Shared by every layout (state): C read+write, meta (D + reception flag)
+# read+write, 16-bit spiking record written, rule offsets read, 16-byte rule
+# records of open neurons read, pending rule read/written around reopening.
+def state_bytes(q, c):
+    return 8 * q + 8 * q + 2 * q + 4 * q + 16 * c["rules_of_open"] + 8 * c["reopening"]
+
+
+def layout_bytes(layout, q, c, emit_w):
+    G, E = c["emit_edges"], c["emitting"]
+    if layout == "csr_pull":
+        # in-list offsets, in-lists of receiving neurons, emitted values written + read once
+        return 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
+    push = 8 * q + 4 * G          # receive buffer read + cleared, one 4-byte update per delivery
+    if layout == "optimized":
+        return push + 4 * (G + E)     # Sy entries of emitters (+ terminator)
+    if layout == "ell":
+        return push + 8 * (G + E)     # (neuron, value) pairs of emitting rules (+ terminator)
+    return push + 4 * G + 8 * E       # csr_push: targets + row bounds
+
+
+def step_bytes(layout, q, c, emit_w):
+    return state_bytes(q, c) + layout_bytes(layout, q, c, emit_w)
+
+
+def emit_width(pmax):
+    w = 1
+    while w < 16 and pmax > (1 << w) - 1:
+        w *= 2
+    return w
+
+
+def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
+    """Times `steps` steps after `warmup` on one system; returns a result dict."""
+    t0 = time.time()
+    g = binding.System.from_spec(spec, layout=layout, chunk=chunk)
+    create_s = time.time() - t0
+    stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps // chunk + 2)]
+    ev[0].record(stream)
+    n_chunks = 0
+    left = steps
+    while left > 0:
+        n = min(chunk, left)
+        g.step(n)
+        n_chunks += 1
+        ev[n_chunks].record(stream)
+        left -= n
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[n_chunks])
+    chunk_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(n_chunks)]
+    done, halted = g.steps_done()
+    g.close()
+    per_step_ms = total_ms / steps
+    full = [c / chunk for c, i in zip(chunk_ms, range(n_chunks)) if (i + 1) * chunk <= steps]
+    return {"layout": layout, "ms_per_step": per_step_ms, "total_ms": total_ms,
+            "steps_done": done, "halted": halted, "create_s": round(create_s, 2),
+            "step_ms_p50": float(np.percentile(full, 50)) if full else per_step_ms,
+            "step_ms_p99": float(np.percentile(full, 99)) if full else per_step_ms}
+
+
+def count_bytes(binding, spec, layout, steps, warmup, emit_w):
+    g = binding.System.from_spec(spec, layout=layout, counters=True, ring=max(4096, steps + 8))
+    g.step(warmup + steps)
+    cnt = g.read_counters(warmup, steps)
+    g.close()
+    b = [step_bytes(layout, spec.q, c, emit_w) for c in cnt]
+    return float(np.mean(b)), cnt
+
+
+def cpu_baseline(spec, seconds):
+    from oracle import oracle as orc
+    o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
+                         spec.select, spec.seed)
+    n = 0
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        n += o.step(5)
+    dt = time.time() - t0
+    return {"value": spec.q * n / dt, "unit": "neuron-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%s: first %d steps, single-threaded C oracle (%.1f s)" % (spec.name, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--layout", default="csr_pull")
+    ap.add_argument("--layouts", default="csr_pull,optimized,ell,csr_push")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-counters", action="store_true")
+    ap.add_argument("--q", type=int, default=1 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the simulator is a single-GPU build "
+              "(no collectives); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2408_04343_amd import binding
+    from paper_2408_04343_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    spec = wl.config2(q=args.q, steps=args.steps)
+    log("generated %s: q=%d m=%d nnz=%d z=%d in %.1fs" % (spec.name, spec.q, spec.m, spec.nnz,
+                                                         spec.max_outdeg(), time.time() - t0))
+    emit_w = emit_width(int(spec.rules[:, 4].max()))
+    layouts = [x for x in args.layouts.split(",") if x]
+    if args.layout not in layouts:
+        layouts.insert(0, args.layout)
+    results = {}
+    for lay in layouts:
+        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk)
+        if not args.no_counters:
+            b, cnt = count_bytes(binding, spec, lay, args.steps, args.warmup, emit_w)
+            r["alg_bytes_per_step"] = b
+            r["alg_GBps"] = b / (r["ms_per_step"] * 1e-3) / 1e9
+            r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
+            if lay == args.layout:
+                r["mean_counters"] = {k: float(np.mean([c[k] for c in cnt])) for k in cnt[0]}
+        r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+        results[lay] = r
+        log("%-10s %.4f ms/step  %.3e nu/s  %s" % (lay, r["ms_per_step"], r["neuron_updates_per_s"],
+                                                   "%.0f GB/s alg" % r["alg_GBps"] if "alg_GBps" in r else ""))
+    head = results[args.layout]
+    value = spec.q * args.steps / (head["total_ms"] * 1e-3)
+    roof = None
+    if "alg_GBps" in head:
+        roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(head["frac_of_peak"], 4), "traffic": None,
+                "kernel": "step_pull_kernel" if args.layout == "csr_pull" else "step_push_kernel",
+                "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
+                "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) for ~%.0f s ..." % args.cpu_seconds)
+        cpu = cpu_baseline(spec, args.cpu_seconds)
+    out = {
+        "metric": METRIC, "value": value, "unit": "neuron-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "q": spec.q, "rules": spec.m, "synapses": spec.nnz,
+                   "max_out_degree": spec.max_outdeg(), "layout": args.layout, "select": "first",
+                   "semantics": "standard", "graph_chunk": args.chunk},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
+                                "over": "graph chunks of %d steps" % args.chunk},
+        "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()
+                        if kk != "mean_counters"} for k, v in results.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

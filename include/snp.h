@@ -130,6 +130,7 @@ typedef struct snp_counters {
   int64_t spikes_lost;   /* of those, spikes that reached a closed neuron    */
   int64_t receiving;     /* neurons open for reception at this step          */
   int64_t reopening;     /* neurons whose delay counter reached zero         */
+  int64_t recv_in_edges; /* in-degrees summed over the receiving neurons     */
 } snp_counters;
 
 typedef struct snp_sys snp_sys;

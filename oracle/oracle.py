@@ -40,7 +40,7 @@ class Rule(ct.Structure):
 class Counters(ct.Structure):
     _fields_ = [(n, ct.c_int64) for n in (
         "open_neurons", "rules_of_open", "selecting", "emitting", "emit_edges",
-        "spikes_sent", "spikes_lost", "receiving", "reopening")]
+        "spikes_sent", "spikes_lost", "receiving", "reopening", "recv_in_edges")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -70,6 +70,7 @@ typedef struct {
   int64_t spikes_lost;      /* of those, spikes that reached a closed target */
   int64_t receiving;        /* neurons open for reception at this step       */
   int64_t reopening;        /* neurons whose delay counter reached zero      */
+  int64_t recv_in_edges;    /* in-degrees summed over receiving neurons      */
 } orc_counters;
 
 typedef struct {
@@ -82,6 +83,7 @@ typedef struct {
   int32_t* rlist;        /*   in increasing rule id                          */
   int32_t* ostart;       /* out-neighbours of i: olist[ostart[i] .. ostart[i+1]) */
   int32_t* olist;
+  int32_t* indeg;        /* in-degree of each neuron                        */
   int64_t* C;            /* spikes per neuron                                */
   int32_t* D;            /* delay counter, 0 = open                          */
   int32_t* pend;         /* rule waiting to emit while D > 0, else -1        */
@@ -177,7 +179,8 @@ int orc_create(int32_t q, const int32_t* spikes0, int32_t m, const orc_rule* rul
   s->recv_open = (int32_t*)malloc(sizeof(int32_t) * (size_t)q);
   s->recv = (int64_t*)malloc(sizeof(int64_t) * (size_t)q);
   s->cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
-  if (!s->rules || !s->rstart || !s->rlist || !s->ostart || !s->olist || !s->C || !s->D ||
+  s->indeg = (int32_t*)calloc((size_t)q, sizeof(int32_t));
+  if (!s->indeg || !s->rules || !s->rstart || !s->rlist || !s->ostart || !s->olist || !s->C || !s->D ||
       !s->pend || !s->S || !s->cons || !s->emit || !s->Dn || !s->recv_open || !s->recv || !s->cand) {
     orc_destroy(s);
     return -2;
@@ -194,7 +197,10 @@ int orc_create(int32_t q, const int32_t* spikes0, int32_t m, const orc_rule* rul
     free(fill);
   }
   /* syn: out-neighbour lists.  syn is a set, so a repeated pair is invalid. */
-  for (int64_t e = 0; e < nsyn; ++e) s->ostart[src[e] + 1]++;
+  for (int64_t e = 0; e < nsyn; ++e) {
+    s->ostart[src[e] + 1]++;
+    s->indeg[dst[e]]++;
+  }
   for (int32_t i = 0; i < q; ++i) s->ostart[i + 1] += s->ostart[i];
   {
     int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)q);
@@ -229,7 +235,7 @@ void orc_destroy(orc_sys* s) {
   if (!s) return;
   free(s->rules); free(s->rstart); free(s->rlist); free(s->ostart); free(s->olist);
   free(s->C); free(s->D); free(s->pend); free(s->S); free(s->cons); free(s->emit);
-  free(s->Dn); free(s->recv_open); free(s->recv); free(s->cand);
+  free(s->Dn); free(s->recv_open); free(s->recv); free(s->cand); free(s->indeg);
   free(s);
 }
 
@@ -321,7 +327,10 @@ static int step_once(orc_sys* s) {
     }
   }
   for (int32_t t = 0; t < q; ++t) {
-    if (s->recv_open[t]) c.receiving++;
+    if (s->recv_open[t]) {
+      c.receiving++;
+      c.recv_in_edges += s->indeg[t];
+    }
     s->C[t] = s->C[t] - s->cons[t] + s->recv[t];
     if (s->C[t] > INT32_MAX) s->overflow = 1;
     s->D[t] = s->Dn[t];

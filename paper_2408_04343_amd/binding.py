@@ -50,7 +50,7 @@ class Rule(ct.Structure):
 
 
 COUNTER_FIELDS = ["open_neurons", "rules_of_open", "selecting", "emitting", "emit_edges",
-                  "spikes_sent", "spikes_lost", "receiving", "reopening"]
+                  "spikes_sent", "spikes_lost", "receiving", "reopening", "recv_in_edges"]
 
 
 class Counters(ct.Structure):

@@ -72,7 +72,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
   p.add(4LL * m);            // slot of caller id
   p.add(sizeof(Ctl));
   p.add(4LL * q * 4);        // materialize outputs
-  p.add(16);                 // digest scratch
+  p.add(32);                 // digest / counter scratch
   if (flags & SNP_F_DIGEST) p.add(8 * ring);
   if (flags & SNP_F_COUNTERS) p.add(8LL * NCOUNT * (ring + 1));
   if (layout == L_CSR_PULL) {
@@ -82,6 +82,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
     p.add(2 * tiles * pull_tile() * emit_w / 32 * 4);
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
   } else {
+    if (flags & SNP_F_COUNTERS) p.add(4LL * q);
     p.add(4LL * q * 2);      // delta[2]
     p.add(4LL * (q + 1));    // out_ptr
     p.add(4LL * std::max<int64_t>(nnz, 1));
@@ -495,7 +496,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   }
   if ((st = alloc_fill(s, (void**)&d.ctl, sizeof(Ctl), 0)) != SNP_OK) return bail(st);
   if ((st = alloc_fill(s, (void**)&s->scratch, 16 * (size_t)q, 0)) != SNP_OK) return bail(st);
-  if ((st = alloc_fill(s, (void**)&s->dig_tmp, 16, 0)) != SNP_OK) return bail(st);
+  if ((st = alloc_fill(s, (void**)&s->dig_tmp, 32, 0)) != SNP_OK) return bail(st);
   if (d.flags & F_DIGEST)
     if ((st = alloc_fill(s, (void**)&d.digests, 8 * (size_t)o.ring, 0)) != SNP_OK) return bail(st);
   if (d.flags & F_COUNTERS)
@@ -522,6 +523,12 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return bail(st);
     int32_t* p;
+    if (d.flags & F_COUNTERS) {
+      std::vector<int32_t> indeg((size_t)q, 0);
+      for (int64_t e = 0; e < nsyn; ++e) indeg[oc[e]]++;
+      if ((st = upload(s, &p, indeg.data(), (size_t)q)) != SNP_OK) return bail(st);
+      d.in_deg = p;
+    }
     if ((st = upload(s, &p, op.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
     d.out_ptr = p;
     if ((st = upload(s, &p, oc.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
@@ -645,12 +652,12 @@ int snp_read_counters(snp_sys* s, snp_counters* out, int64_t first, int64_t coun
   if (count > 0 && first < si.kx - R + 1) return fail(SNP_EINVAL, "counters no longer in the ring");
   std::vector<unsigned long long> ring((size_t)R * NCOUNT);
   HIPCHK(hipMemcpy(ring.data(), s->d.counters, 8 * (size_t)R * NCOUNT, hipMemcpyDeviceToHost));
-  unsigned long long tail[2] = {0, 0};
+  unsigned long long tail[3] = {0, 0, 0};
   if (first + count == si.steps && si.steps == si.kx) {
     // the reception of the last executed step is still pending: count it now
-    HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 16, s->stream));
+    HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 24, s->stream));
     HIPCHK(launch_recv_counts(s->d, si.rbuf, s->dig_tmp, s->stream));
-    HIPCHK(hipMemcpyAsync(tail, s->dig_tmp, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(tail, s->dig_tmp, 24, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
   }
   for (int64_t t = first; t < first + count; ++t) {
@@ -660,6 +667,7 @@ int snp_read_counters(snp_sys* s, snp_counters* out, int64_t first, int64_t coun
     if (t == si.steps - 1 && si.steps == si.kx) {
       v[6] = (int64_t)tail[0];  // spikes_lost
       v[7] = (int64_t)tail[1];  // receiving
+      v[9] = (int64_t)tail[2];  // recv_in_edges
     }
     snp_counters& o = out[t - first];
     o.open_neurons = v[0];
@@ -671,6 +679,7 @@ int snp_read_counters(snp_sys* s, snp_counters* out, int64_t first, int64_t coun
     o.spikes_lost = v[6];
     o.receiving = v[7];
     o.reopening = v[8];
+    o.recv_in_edges = v[9];
   }
   return SNP_OK;
 }

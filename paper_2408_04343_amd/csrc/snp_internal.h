@@ -16,7 +16,7 @@ enum : uint32_t { F_DIGEST = 1u, F_COUNTERS = 2u };
 constexpr uint32_t META_RECV = 0x80000000u;
 constexpr uint32_t META_D = 0x7FFFFFFFu;
 constexpr uint16_t S_NONE = 0xFFFFu;
-constexpr int NCOUNT = 9;  // fields of snp_counters
+constexpr int NCOUNT = 10;  // fields of snp_counters
 
 // One rule of the rule vector RV in neuron order (16 bytes).
 //   Applicability of E = a^base (a^period)* together with n >= c is
@@ -64,6 +64,7 @@ struct SysDev {
   const int32_t* out_ptr;    // CSR_PUSH: [q+1]
   const int32_t* out_col;    // CSR_PUSH: [nnz]
   const int32_t* out_deg;    // counters only: [q]
+  const int32_t* in_deg;     // counters only, push layouts: [q]
   // pull representation
   const int32_t* in_ptr;     // [q+1]
   const int32_t* in_src;     // [nnz], each list in increasing source id

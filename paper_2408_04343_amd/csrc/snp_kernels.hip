@@ -97,7 +97,7 @@ struct Cnt {
     for (int x = 0; x < NCOUNT; ++x) v[x] = 0;
   }
 };
-enum { C_OPEN = 0, C_RULES, C_SEL, C_EMIT, C_EDGES, C_SENT, C_LOST, C_RECV, C_REOPEN };
+enum { C_OPEN = 0, C_RULES, C_SEL, C_EMIT, C_EDGES, C_SENT, C_LOST, C_RECV, C_REOPEN, C_INEDGES };
 
 __device__ __forceinline__ uint64_t digest_term(int32_t i, int32_t C, int32_t D, int32_t S) {
   const uint64_t key = (uint64_t)(uint32_t)i * 0x9E3779B97F4A7C15ull;
@@ -218,7 +218,10 @@ __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j)
         const uint32_t sum = (uint32_t)C + (uint32_t)recv;
         if ((int32_t)sum < 0) s.ctl->overflow = 1;
         C = (int32_t)sum;
-        if (CNT) cnt.v[C_RECV] += 1;
+        if (CNT) {
+          cnt.v[C_RECV] += 1;
+          cnt.v[C_INEDGES] += (unsigned long long)s.in_deg[i];
+        }
       } else if (CNT) {
         cnt.v[C_LOST] += (unsigned long long)recv;
       }
@@ -263,7 +266,7 @@ __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j)
     unsigned long long* cs = s.counters + (k % s.ring) * NCOUNT;
     unsigned long long* cp = s.counters + (((k - 1) % s.ring + s.ring) % s.ring) * NCOUNT;
     for (int x = 0; x < NCOUNT; ++x) {
-      const bool recv_side = (x == C_LOST || x == C_RECV);
+      const bool recv_side = (x == C_LOST || x == C_RECV || x == C_INEDGES);
       if (recv_side && k == 0) continue;
       block_add64<PUSH_NT>(cnt.v[x], recv_side ? &cp[x] : &cs[x], red);
     }
@@ -354,7 +357,10 @@ __global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j)
         const uint32_t sum = (uint32_t)C + (uint32_t)recv[r];
         if ((int32_t)sum < 0) s.ctl->overflow = 1;
         C = (int32_t)sum;
-        if (CNT) cnt.v[C_RECV] += 1;
+        if (CNT) {
+          cnt.v[C_RECV] += 1;
+          cnt.v[C_INEDGES] += (unsigned long long)(s.in_ptr[t + 1] - s.in_ptr[t]);
+        }
       } else if (CNT) {
         cnt.v[C_LOST] += (unsigned long long)recv[r];
       }
@@ -384,7 +390,7 @@ __global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j)
     unsigned long long* cs = s.counters + (k % s.ring) * NCOUNT;
     unsigned long long* cp = s.counters + (((k - 1) % s.ring + s.ring) % s.ring) * NCOUNT;
     for (int x = 0; x < NCOUNT; ++x) {
-      const bool recv_side = (x == C_LOST || x == C_RECV);
+      const bool recv_side = (x == C_LOST || x == C_RECV || x == C_INEDGES);
       if (recv_side && k == 0) continue;
       block_add64<PULL_NT>(cnt.v[x], recv_side ? &cp[x] : &cs[x], red);
     }
@@ -522,11 +528,12 @@ hipError_t launch_activity(const SysDev& s, const int32_t* C, const int32_t* D, 
 }
 
 // Reception-side counters (spikes lost at closed neurons, receiving neurons)
-// of the step whose deliveries sit in buffer rbuf.  out2 must be 0 on entry.
+// and in-edges of receiving neurons, of the step whose deliveries sit in
+// buffer rbuf.  out2[0..2] must be 0 on entry.
 __global__ void recv_counts_kernel(SysDev s, int32_t rbuf, unsigned long long* out2) {
   __shared__ unsigned long long red[4];
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
-  unsigned long long lost = 0, recv = 0;
+  unsigned long long lost = 0, recv = 0, inedges = 0;
   if (i < s.q && rbuf >= 0) {
     const uint32_t meta = s.meta[i];
     int32_t got = 0;
@@ -541,11 +548,16 @@ __global__ void recv_counts_kernel(SysDev s, int32_t rbuf, unsigned long long* o
     } else {
       got = s.delta[rbuf][i];
     }
-    if (meta & META_RECV) recv = 1;
-    else lost = (unsigned long long)got;
+    if (meta & META_RECV) {
+      recv = 1;
+      inedges = (unsigned long long)(s.layout == L_CSR_PULL ? s.in_ptr[i + 1] - s.in_ptr[i] : s.in_deg[i]);
+    } else {
+      lost = (unsigned long long)got;
+    }
   }
   block_add64<256>(lost, &out2[0], red);
   block_add64<256>(recv, &out2[1], red);
+  block_add64<256>(inedges, &out2[2], red);
 }
 
 hipError_t launch_recv_counts(const SysDev& s, int32_t rbuf, unsigned long long* out2,

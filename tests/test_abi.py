@@ -86,7 +86,7 @@ def test_rules_array_layout_matches_header():
     from paper_2408_04343_amd import binding
     import ctypes as ct
     assert ct.sizeof(binding.Rule) == 24
-    assert ct.sizeof(binding.Counters) == 72
+    assert ct.sizeof(binding.Counters) == 80
     o = binding.Opts()
     binding.lib.snp_opts_default(ct.byref(o))
     assert (o.layout, o.select, o.semantics, o.chunk, o.device) == (0, 0, 0, 64, -1)
