@@ -32,10 +32,11 @@ def log(*a):
 
 # Algorithmic bytes of one step, from the exact per-step work counters.
 # Shared by every layout (state): C read+write, meta (D + reception flag)
-# read+write, 16-bit spiking record written, rule offsets read, 16-byte rule
-# records of open neurons read, pending rule read/written around reopening.
-def state_bytes(q, c):
-    return 8 * q + 8 * q + 2 * q + 4 * q + 16 * c["rules_of_open"] + 8 * c["reopening"]
+# read+write, 16-bit spiking record written, rule offsets read, the rule
+# records (R bytes each) of open neurons read, pending rule read/written
+# around reopening.
+def state_bytes(q, c, rule_bytes):
+    return 8 * q + 8 * q + 2 * q + 4 * q + rule_bytes * c["rules_of_open"] + 8 * c["reopening"]
 
 
 def layout_bytes(layout, q, c, emit_w):
@@ -51,22 +52,16 @@ def layout_bytes(layout, q, c, emit_w):
     return push + 4 * G + 8 * E       # csr_push: targets + row bounds
 
 
-def step_bytes(layout, q, c, emit_w):
-    return state_bytes(q, c) + layout_bytes(layout, q, c, emit_w)
+def step_bytes(layout, q, c, info):
+    return state_bytes(q, c, info["rule_bytes"]) + layout_bytes(layout, q, c, info["emit_bits"])
 
 
-def emit_width(pmax):
-    w = 1
-    while w < 16 and pmax > (1 << w) - 1:
-        w *= 2
-    return w
-
-
-def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
+def run_layout(binding, torch, spec, layout, steps, warmup, chunk, tile_log2):
     """Times `steps` steps after `warmup` on one system; returns a result dict."""
     t0 = time.time()
-    g = binding.System.from_spec(spec, layout=layout, chunk=chunk)
+    g = binding.System.from_spec(spec, layout=layout, chunk=chunk, pull_tile_log2=tile_log2)
     create_s = time.time() - t0
+    info = g.info()
     stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
     g.step(warmup)
     torch.cuda.synchronize()
@@ -87,18 +82,18 @@ def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
     g.close()
     per_step_ms = total_ms / steps
     full = [c / chunk for c, i in zip(chunk_ms, range(n_chunks)) if (i + 1) * chunk <= steps]
-    return {"layout": layout, "ms_per_step": per_step_ms, "total_ms": total_ms,
+    return {"layout": layout, "info": info, "ms_per_step": per_step_ms, "total_ms": total_ms,
             "steps_done": done, "halted": halted, "create_s": round(create_s, 2),
             "step_ms_p50": float(np.percentile(full, 50)) if full else per_step_ms,
             "step_ms_p99": float(np.percentile(full, 99)) if full else per_step_ms}
 
 
-def count_bytes(binding, spec, layout, steps, warmup, emit_w):
+def count_bytes(binding, spec, layout, steps, warmup, info):
     g = binding.System.from_spec(spec, layout=layout, counters=True, ring=max(4096, steps + 8))
     g.step(warmup + steps)
     cnt = g.read_counters(warmup, steps)
     g.close()
-    b = [step_bytes(layout, spec.q, c, emit_w) for c in cnt]
+    b = [step_bytes(layout, spec.q, c, info) for c in cnt]
     return float(np.mean(b)), cnt
 
 
@@ -127,6 +122,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--q", type=int, default=1 << 20)
+    ap.add_argument("--pull-tile-log2", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator is a single-GPU build "
@@ -142,15 +138,15 @@ def main():
     spec = wl.config2(q=args.q, steps=args.steps)
     log("generated %s: q=%d m=%d nnz=%d z=%d in %.1fs" % (spec.name, spec.q, spec.m, spec.nnz,
                                                          spec.max_outdeg(), time.time() - t0))
-    emit_w = emit_width(int(spec.rules[:, 4].max()))
     layouts = [x for x in args.layouts.split(",") if x]
     if args.layout not in layouts:
         layouts.insert(0, args.layout)
     results = {}
     for lay in layouts:
-        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk)
+        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk,
+                       args.pull_tile_log2)
         if not args.no_counters:
-            b, cnt = count_bytes(binding, spec, lay, args.steps, args.warmup, emit_w)
+            b, cnt = count_bytes(binding, spec, lay, args.steps, args.warmup, r["info"])
             r["alg_bytes_per_step"] = b
             r["alg_GBps"] = b / (r["ms_per_step"] * 1e-3) / 1e9
             r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
@@ -180,7 +176,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "q": spec.q, "rules": spec.m, "synapses": spec.nnz,
                    "max_out_degree": spec.max_outdeg(), "layout": args.layout, "select": "first",
-                   "semantics": "standard", "graph_chunk": args.chunk},
+                   "semantics": "standard", "graph_chunk": args.chunk,
+                   "pull_tile_log2": head["info"].get("pull_tile_log2"),
+                   "rule_bytes": head["info"].get("rule_bytes")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],

@@ -102,6 +102,8 @@ typedef struct snp_opts {
   uint32_t flags;      /* SNP_F_*                                            */
   int32_t device;      /* HIP device ordinal; -1 = current device            */
   int64_t ring;        /* entries kept by the digest / counter rings; 0 = 4096 */
+  int32_t pull_tile_log2; /* CSR_PULL: log2 of the neurons one block owns, 11
+                             (two blocks per compute unit) or 12 (one); 0 = 12 */
   snp_alloc_fn alloc;
   snp_free_fn free;
   void* alloc_ctx;
@@ -216,8 +218,21 @@ int snp_write_state(snp_sys* sys, const int32_t* config, const int32_t* delays,
  * size required.                                                           */
 int snp_read_layout(snp_sys* sys, int32_t which, int32_t* out, int64_t count, int64_t* needed);
 
-/* Shape of the handle: q, m, synapses, MaxOutDegree, layout in use. */
-int snp_info(snp_sys* sys, int32_t* q, int32_t* m, int64_t* nsyn, int32_t* zmax, int32_t* layout);
+/* Shape and device representation of a handle. */
+typedef struct snp_info_t {
+  int32_t q, m;          /* neurons, rules                                   */
+  int64_t nsyn;          /* synapses                                         */
+  int32_t zmax;          /* MaxOutDegree                                     */
+  int32_t layout;        /* SNP_LAYOUT_* in use                              */
+  int32_t rule_bytes;    /* bytes per rule record on the device (8 or 16)    */
+  int32_t emit_bits;     /* CSR_PULL: bits per emitted value                 */
+  int32_t pull_tile_log2;/* CSR_PULL: log2 of the neurons per block          */
+  int32_t pull_chunk;    /* CSR_PULL: sources per LDS chunk                  */
+  int32_t pull_chunks;   /* CSR_PULL: number of source chunks                */
+  int32_t pad;
+  int64_t device_bytes;  /* device memory held by the handle                 */
+} snp_info_t;
+int snp_info(snp_sys* sys, snp_info_t* out);
 
 /* Device bytes a system of this shape needs in `layout` with `flags` and a
  * ring of `ring` entries (0 = 4096), as snp_create allocates them.        */

@@ -41,6 +41,7 @@ class Opts(ct.Structure):
     _fields_ = [("layout", ct.c_int32), ("select", ct.c_int32), ("semantics", ct.c_int32),
                 ("chunk", ct.c_int32), ("seed", ct.c_uint64), ("stream", ct.c_void_p),
                 ("flags", ct.c_uint32), ("device", ct.c_int32), ("ring", ct.c_int64),
+                ("pull_tile_log2", ct.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ct.c_void_p)]
 
 
@@ -55,6 +56,13 @@ COUNTER_FIELDS = ["open_neurons", "rules_of_open", "selecting", "emitting", "emi
 
 class Counters(ct.Structure):
     _fields_ = [(n, ct.c_int64) for n in COUNTER_FIELDS]
+
+
+class Info(ct.Structure):
+    _fields_ = [("q", ct.c_int32), ("m", ct.c_int32), ("nsyn", ct.c_int64), ("zmax", ct.c_int32),
+                ("layout", ct.c_int32), ("rule_bytes", ct.c_int32), ("emit_bits", ct.c_int32),
+                ("pull_tile_log2", ct.c_int32), ("pull_chunk", ct.c_int32),
+                ("pull_chunks", ct.c_int32), ("pad", ct.c_int32), ("device_bytes", ct.c_int64)]
 
 
 class SnpError(RuntimeError):
@@ -86,7 +94,7 @@ def _load():
         "snp_read_counters": (ct.c_int, [vp, P(Counters), ct.c_int64, ct.c_int64]),
         "snp_write_state": (ct.c_int, [vp, i32p, i32p, i32p, i32p, ct.c_int64]),
         "snp_read_layout": (ct.c_int, [vp, ct.c_int32, i32p, ct.c_int64, i64p]),
-        "snp_info": (ct.c_int, [vp, i32p, i32p, i64p, i32p, i32p]),
+        "snp_info": (ct.c_int, [vp, P(Info)]),
         "snp_footprint": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
                                      ct.c_uint32, ct.c_int64, i64p]),
         "snp_paper_sizes": (ct.c_int, [ct.c_int64, ct.c_int64, ct.c_int64, i64p, i64p, i64p]),
@@ -172,7 +180,7 @@ class System:
 
     def __init__(self, q, spikes0, rules, src, dst, *, layout="auto", select="first",
                  semantics="standard", seed=0, chunk=64, digest=False, counters=False,
-                 graph=True, ring=0, device=None, memory="auto", stream=None):
+                 graph=True, ring=0, device=None, memory="auto", stream=None, pull_tile_log2=0):
         self._h = ct.c_void_p()
         self.q = int(q)
         s0 = _i32(spikes0)
@@ -190,6 +198,7 @@ class System:
         o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         o.flags = (F_DIGEST if digest else 0) | (F_COUNTERS if counters else 0) | (0 if graph else F_NO_GRAPH)
         o.ring = int(ring)
+        o.pull_tile_log2 = int(pull_tile_log2)
         o.device = -1 if device is None else int(device)
         torch = _torch_cuda()
         self._torch_stream = None
@@ -304,7 +313,6 @@ class System:
         return out[:need.value]
 
     def info(self):
-        q, m, z, lay = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
-        n = ct.c_int64()
-        _check(lib.snp_info(self._h, ct.byref(q), ct.byref(m), ct.byref(n), ct.byref(z), ct.byref(lay)))
-        return {"q": q.value, "m": m.value, "nsyn": n.value, "zmax": z.value, "layout": lay.value}
+        i = Info()
+        _check(lib.snp_info(self._h, ct.byref(i)))
+        return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "pad"}

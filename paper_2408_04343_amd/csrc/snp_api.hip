@@ -7,6 +7,7 @@
 // device (Sec. 4; Tables 2 and 3).  snp_step enqueues step kernels, in
 // captured graphs of `chunk` steps when it can.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -37,7 +38,7 @@ int fail(int status, const std::string& msg) {
 
 constexpr int64_t kDefaultRing = 4096;
 constexpr int32_t kDefaultChunk = 64;
-constexpr int32_t kPullLdsBytes = 60 * 1024;  // LDS for one chunk of emitted values
+constexpr int32_t kPullLdsBytes = 160 * 1024;  // LDS of one pull block (gfx950 maximum)
 
 int32_t emit_width(int32_t pmax) {
   int32_t w = 1;
@@ -45,12 +46,21 @@ int32_t emit_width(int32_t pmax) {
   return w;
 }
 
-int32_t pull_chunk_sources(int32_t w) {
-  const int64_t stage = (int64_t)pull_tile() * w / 32 * 4;
-  int64_t words = (kPullLdsBytes - stage) / 4;
-  int64_t src = words * 32 / w;
-  src -= src % 32;
-  return (int32_t)std::max<int64_t>(32, src);
+// LDS budget of one pull block: the whole CU for 4096-neuron tiles (one
+// block per CU), half of it for 2048-neuron tiles (two blocks per CU).
+int64_t pull_lds_budget(int32_t tb) { return tb >= 12 ? kPullLdsBytes : kPullLdsBytes / 2; }
+
+// Sources per LDS chunk of emitted values: what is left of the block's LDS
+// after the accumulator and the staging words, below 2^(32 - tile bits) so
+// that a source offset fits in an edge record and no record equals the
+// padding 0xFFFFFFFF.
+int32_t pull_chunk_sources(int32_t w, int32_t tb) {
+  const int64_t tile = 1LL << tb;
+  const int64_t fixed = tile * 4 + tile * w / 8 + 2048;
+  int64_t src = (pull_lds_budget(tb) - fixed) * 8 / w;
+  src = std::min<int64_t>(src, (1LL << (32 - tb)) - 128);
+  src -= src % 128;  // chunk starts stay 16-byte aligned in the emit vector
+  return (int32_t)std::max<int64_t>(128, src);
 }
 
 struct Plan {
@@ -60,14 +70,14 @@ struct Plan {
 
 // Device bytes of a system; mirrors the allocations of snp_create.
 int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout, uint32_t flags,
-                   int64_t ring, int32_t emit_w) {
+                   int64_t ring, int32_t emit_w, int32_t tb) {
   Plan p;
   p.add(4LL * q);            // C
   p.add(4LL * q);            // meta
   p.add(4LL * q);            // pend
   p.add(2LL * q * 2);        // S16[2]
   p.add(4LL * (q + 1));      // rs
-  p.add(16LL * m);           // rules
+  p.add(16LL * m);           // rules (at most 16 bytes each)
   p.add(4LL * m);            // rid
   p.add(4LL * m);            // slot of caller id
   p.add(sizeof(Ctl));
@@ -76,10 +86,14 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
   if (flags & SNP_F_DIGEST) p.add(8 * ring);
   if (flags & SNP_F_COUNTERS) p.add(8LL * NCOUNT * (ring + 1));
   if (layout == L_CSR_PULL) {
-    const int64_t tiles = (q + pull_tile() - 1) / pull_tile();
+    const int64_t tile = 1LL << tb;
+    const int64_t tiles = (q + tile - 1) / tile;
+    const int64_t nc = (q + pull_chunk_sources(emit_w, tb) - 1) / pull_chunk_sources(emit_w, tb);
     p.add(4LL * (q + 1));
     p.add(4LL * std::max<int64_t>(nnz, 1));
-    p.add(2 * tiles * pull_tile() * emit_w / 32 * 4);
+    p.add(4LL * (std::max<int64_t>(nnz, 1) + 3 * tiles * nc + 4));   // blocked in-edges (padded)
+    p.add(4LL * (tiles * nc + 1));
+    p.add(2 * tiles * tile * emit_w / 32 * 4);
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
   } else {
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
@@ -111,6 +125,7 @@ struct snp_sys {
   hipGraphExec_t graph = nullptr;
   bool graph_tried = false;
   int in_batch = 0;
+  int64_t device_bytes = 0;
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 4;
@@ -121,7 +136,10 @@ struct snp_sys {
       (void)hipGetLastError();
       p = nullptr;
     }
-    if (p) allocs.push_back(p);
+    if (p) {
+      allocs.push_back(p);
+      device_bytes += (int64_t)bytes;
+    }
     return p;
   }
   void release() {
@@ -302,7 +320,7 @@ int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layo
   if (q < 1 || m < 0 || nsyn < 0 || zmax < 0 || !bytes) return fail(SNP_EINVAL, "bad shape");
   if (layout == SNP_LAYOUT_AUTO) layout = SNP_LAYOUT_CSR_PULL;
   if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
-  *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16);
+  *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16, 12);
   return SNP_OK;
 }
 
@@ -475,7 +493,8 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   d.seed = o.seed;
   d.ring = o.ring;
   d.emit_w = emit_width(pmax_all);
-  d.pull_chunk = pull_chunk_sources(d.emit_w);
+  d.pull_tb = o.pull_tile_log2 == 11 ? 11 : 12;
+  d.pull_chunk = pull_chunk_sources(d.emit_w, d.pull_tb);
 
   int st;
   if ((st = upload(s, &d.C, spikes0, (size_t)q)) != SNP_OK) return bail(st);
@@ -487,9 +506,32 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     int32_t* p;
     if ((st = upload(s, &p, rs.data(), rs.size())) != SNP_OK) return bail(st);
     d.rs = p;
-    RuleRec* rp;
-    if ((st = upload(s, &rp, rec.data(), (size_t)m)) != SNP_OK) return bail(st);
-    d.rules = rp;
+    // packed 8-byte records when every rule fits them
+    bool fits8 = true;
+    for (int32_t x = 0; x < m && fits8; ++x) {
+      const RuleRec& R = rec[x];
+      const bool dead = R.period == 0 && R.lo < 0;
+      fits8 = (dead || (R.lo >= 0 && R.lo < (1 << 24) && R.period < (int32_t)R8_DEAD)) && R.c < (1 << 16) &&
+              (R.pd & 0xFFFFu) < 256u && (R.pd >> 16) < 256u;
+    }
+    if (fits8) {
+      std::vector<uint2> r8((size_t)std::max(m, 1));
+      for (int32_t x = 0; x < m; ++x) {
+        const RuleRec& R = rec[x];
+        const bool dead = R.period == 0 && R.lo < 0;
+        r8[x].x = dead ? (R8_DEAD << 24) : (((uint32_t)R.period << 24) | (uint32_t)R.lo);
+        r8[x].y = (uint32_t)R.c | ((R.pd & 0xFFu) << 16) | ((R.pd >> 16) << 24);
+      }
+      uint2* rp;
+      if ((st = upload(s, &rp, r8.data(), (size_t)m)) != SNP_OK) return bail(st);
+      d.rules8 = rp;
+      d.rule_bytes = 8;
+    } else {
+      RuleRec* rp;
+      if ((st = upload(s, &rp, rec.data(), (size_t)m)) != SNP_OK) return bail(st);
+      d.rules = rp;
+      d.rule_bytes = 16;
+    }
     if ((st = upload(s, &p, s->h_rid.data(), (size_t)m)) != SNP_OK) return bail(st);
     d.rid = p;
     if ((st = upload(s, &s->slot_of, s->h_slot.data(), (size_t)m)) != SNP_OK) return bail(st);
@@ -509,8 +551,49 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.in_ptr = p;
     if ((st = upload(s, &p, s->h_in_src.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
     d.in_src = p;
-    const size_t tiles = ((size_t)q + pull_tile() - 1) / pull_tile();
-    const size_t words = tiles * (size_t)pull_tile() * d.emit_w / 32;
+    {
+      // in-edges blocked by (target tile, source chunk), each segment sorted
+      const int64_t T = 1LL << d.pull_tb, CS = d.pull_chunk;
+      const int64_t nb = ((int64_t)q + T - 1) / T, nc = ((int64_t)q + CS - 1) / CS;
+      d.pull_nc = (int32_t)nc;
+      std::vector<int32_t> seg((size_t)(nb * nc + 1), 0);
+      const std::vector<int32_t>& ip = s->h_in_ptr;
+      const std::vector<int32_t>& is = s->h_in_src;
+      for (int32_t t = 0; t < q; ++t)
+        for (int32_t e = ip[t]; e < ip[(size_t)t + 1]; ++e) seg[(size_t)((t / T) * nc + is[e] / CS) + 1]++;
+      int64_t total = 0;
+      for (size_t x = 0; x + 1 < seg.size(); ++x) {
+        const int64_t n = ((int64_t)seg[x + 1] + 3) / 4 * 4;  // padded to whole 16-byte groups
+        seg[x] = (int32_t)total;
+        total += n;
+      }
+      seg.back() = (int32_t)total;
+      if (total > 0x7FFFFFF0LL) return bail(fail(SNP_ENOTSUP, "too many in-edges for the pull layout"));
+      std::vector<uint32_t> rec((size_t)std::max<int64_t>(total, 4), 0xFFFFFFFFu);
+      std::vector<int32_t> fill(seg.begin(), seg.end() - 1);
+      for (int32_t t = 0; t < q; ++t)
+        for (int32_t e = ip[t]; e < ip[(size_t)t + 1]; ++e) {
+          const int64_t c = is[e] / CS;
+          rec[(size_t)fill[(size_t)((t / T) * nc + c)]++] =
+              ((uint32_t)(is[e] - c * CS) << d.pull_tb) | (uint32_t)(t % T);
+        }
+      for (size_t x = 0; x + 1 < seg.size(); ++x) std::sort(rec.begin() + seg[x], rec.begin() + seg[x + 1]);
+      uint32_t* pe;
+      if ((st = upload(s, &pe, rec.data(), rec.size())) != SNP_OK) return bail(st);
+      d.pedge = pe;
+      if ((st = upload(s, &p, seg.data(), seg.size())) != SNP_OK) return bail(st);
+      d.pseg = p;
+      static std::atomic<uint64_t> lds_ready{0};  // one bit per device
+      const uint64_t bit = 1ull << (s->dev & 63);
+      if (!(lds_ready.load() & bit)) {
+        if (prepare_pull_kernels(kPullLdsBytes - 1024) != hipSuccess)
+          return bail(fail(SNP_EDEVICE, "cannot raise the LDS limit of the pull kernels"));
+        lds_ready.fetch_or(bit);
+      }
+    }
+    const size_t tile = (size_t)1 << d.pull_tb;
+    const size_t tiles = ((size_t)q + tile - 1) / tile;
+    const size_t words = tiles * tile * d.emit_w / 32;
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.emit[b], 4 * words, 0)) != SNP_OK) return bail(st);
     if (d.flags & F_COUNTERS) {
@@ -717,8 +800,9 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
                         S ? tmp + 3 * (size_t)q : nullptr, s->slot_of, s->stream));
   // nothing is in flight towards the restored state
   if (s->layout == SNP_LAYOUT_CSR_PULL) {
-    const size_t tiles = ((size_t)q + pull_tile() - 1) / pull_tile();
-    const size_t words = tiles * (size_t)pull_tile() * s->d.emit_w / 32;
+    const size_t tile = (size_t)1 << s->d.pull_tb;
+    const size_t tiles = ((size_t)q + tile - 1) / tile;
+    const size_t words = tiles * tile * s->d.emit_w / 32;
     for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.emit[b], 0, 4 * words, s->stream));
   } else {
     for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.delta[b], 0, 4 * (size_t)q, s->stream));
@@ -774,13 +858,20 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
   return SNP_OK;
 }
 
-int snp_info(snp_sys* s, int32_t* q, int32_t* m, int64_t* nsyn, int32_t* zmax, int32_t* layout) {
-  if (!s) return fail(SNP_EINVAL, "null handle");
-  if (q) *q = s->q;
-  if (m) *m = s->m;
-  if (nsyn) *nsyn = s->nnz;
-  if (zmax) *zmax = s->z;
-  if (layout) *layout = s->layout;
+int snp_info(snp_sys* s, snp_info_t* o) {
+  if (!s || !o) return fail(SNP_EINVAL, "null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->q = s->q;
+  o->m = s->m;
+  o->nsyn = s->nnz;
+  o->zmax = s->z;
+  o->layout = s->layout;
+  o->rule_bytes = s->d.rule_bytes;
+  o->emit_bits = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.emit_w : 0;
+  o->pull_tile_log2 = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_tb : 0;
+  o->pull_chunk = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_chunk : 0;
+  o->pull_chunks = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_nc : 0;
+  o->device_bytes = s->device_bytes;
   return SNP_OK;
 }
 

@@ -31,6 +31,12 @@ struct RuleRec {
   uint32_t pd;  // p | d << 16
 };
 
+// Packed 8-byte record, used when every rule has lo < 2^24, period < 255,
+// c < 2^16, p < 2^8 and d < 2^8:
+//   x = period << 24 | lo   (period field R8_DEAD: the rule never applies)
+//   y = c | p << 16 | d << 24
+constexpr uint32_t R8_DEAD = 0xFFu;
+
 // Control block of one system, in device memory.
 struct Ctl {
   int64_t k_base;     // system-local index of launch 0 of the current run of launches
@@ -55,7 +61,9 @@ struct SysDev {
   uint16_t* S16[2];          // local index of the rule selected at step k (k & 1)
   // rule vector, neuron-rule map
   const int32_t* rs;         // [q+1] rules of neuron i: slots rs[i] .. rs[i+1]-1
+  int32_t rule_bytes;        // 8: rules8 holds the rule vector, 16: rules does
   const RuleRec* rules;      // [m] in slot order
+  const uint2* rules8;       // [m] in slot order, packed
   const int32_t* rid;        // [m] caller id of each slot
   // push representations
   int32_t* delta[2];         // spikes received at step k, by k & 1
@@ -66,10 +74,14 @@ struct SysDev {
   const int32_t* out_deg;    // counters only: [q]
   const int32_t* in_deg;     // counters only, push layouts: [q]
   // pull representation
-  const int32_t* in_ptr;     // [q+1]
+  const int32_t* in_ptr;     // [q+1] in-neighbour lists (reads and counters)
   const int32_t* in_src;     // [nnz], each list in increasing source id
+  const uint32_t* pedge;     // [nnz] in-edges by (tile, source chunk): src offset << 12 | target offset
+  const int32_t* pseg;       // [tiles * pull_nc + 1] start of each (tile, chunk) segment
   uint32_t* emit[2];         // packed emit_w-bit values by k & 1
   int32_t pull_chunk;        // sources per LDS chunk
+  int32_t pull_nc;           // number of source chunks
+  int32_t pull_tb;           // log2 of the neurons per block (tile)
   // bookkeeping
   Ctl* ctl;
   uint64_t* digests;         // ring [ring]
@@ -93,8 +105,7 @@ hipError_t launch_activity(const SysDev& s, const int32_t* C, const int32_t* D, 
                            hipStream_t st);
 hipError_t launch_recv_counts(const SysDev& s, int32_t rbuf, unsigned long long* out2,
                               hipStream_t st);
-int pull_threads();
-int pull_tile();
+hipError_t prepare_pull_kernels(size_t bytes);
 size_t pull_lds_bytes(const SysDev& s);
 
 }  // namespace snp

@@ -18,6 +18,8 @@
 //                   target sums the values of its in-neighbours (no atomics).
 // Consecutive launches are the only grid-wide dependency: a step needs every
 // delivery of the previous step, and nothing else from other neurons.
+#include <algorithm>
+
 #include "snp_internal.h"
 
 namespace snp {
@@ -34,29 +36,73 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z;
 }
 
-__device__ __forceinline__ bool rule_applies(const RuleRec& r, int32_t n) {
+// Buffer b (0 or 1) of a double-buffered array member, chosen without
+// indexing the kernel argument (which would copy it to scratch memory).
+template <class T>
+__device__ __forceinline__ T pick(T a0, T a1, int64_t b) {
+  return (b & 1) ? a1 : a0;
+}
+
+// A decoded rule of the rule vector.
+struct Rule {
+  int32_t lo, period, c, p, d;
+};
+
+// Rule records: RB = 16, struct RuleRec; RB = 8, packed uint2 (see
+// snp_internal.h for the two encodings).
+template <int RB>
+__device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
+  Rule r;
+  if (RB == 16) {
+    const RuleRec x = s.rules[slot];
+    r.lo = x.lo;
+    r.period = x.period;
+    r.c = x.c;
+    r.p = (int32_t)(x.pd & 0xFFFFu);
+    r.d = (int32_t)(x.pd >> 16);
+  } else {
+    const uint2 x = s.rules8[slot];
+    const uint32_t per = x.x >> 24;
+    r.lo = per == R8_DEAD ? -1 : (int32_t)(x.x & 0xFFFFFFu);
+    r.period = per == R8_DEAD ? 0 : (int32_t)per;
+    r.c = (int32_t)(x.y & 0xFFFFu);
+    r.p = (int32_t)((x.y >> 16) & 0xFFu);
+    r.d = (int32_t)(x.y >> 24);
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   if (r.period == 0) return n == r.lo;
   if (n < r.lo) return false;
   if (r.period == 1) return true;
   return ((uint32_t)(n - r.lo) % (uint32_t)r.period) == 0u;
 }
 
-// Rule chosen by open neuron i holding n spikes at step k, or -1.
+// Rule chosen by open neuron i holding n spikes at step k, or -1.  `first`
+// is the already loaded record of slot r0 (valid if r0 < r1).
+template <int RB>
 __device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64_t k, int32_t n,
-                                               int32_t r0, int32_t r1) {
+                                               int32_t r0, int32_t r1, const Rule& first) {
+  if (r0 >= r1) return -1;
   if (s.sel == SEL_FIRST) {
-    for (int32_t r = r0; r < r1; ++r)
-      if (rule_applies(s.rules[r], n)) return r;
+    if (rule_applies(first, n)) return r0;
+    for (int32_t r = r0 + 1; r < r1; ++r)
+      if (rule_applies(load_rule<RB>(s, r), n)) return r;
     return -1;
   }
-  uint32_t cnt = 0;
-  for (int32_t r = r0; r < r1; ++r) cnt += rule_applies(s.rules[r], n) ? 1u : 0u;
+  uint32_t cnt = rule_applies(first, n) ? 1u : 0u;
+  for (int32_t r = r0 + 1; r < r1; ++r) cnt += rule_applies(load_rule<RB>(s, r), n) ? 1u : 0u;
   if (cnt == 0) return -1;
   const uint64_t key = ((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)i;
   const uint64_t h = mix64(mix64(s.seed) ^ key);
   uint32_t j = (uint32_t)(((h >> 32) * (uint64_t)cnt) >> 32);
-  for (int32_t r = r0; r < r1; ++r) {
-    if (rule_applies(s.rules[r], n)) {
+  if (rule_applies(first, n)) {
+    if (j == 0) return r0;
+    --j;
+  }
+  for (int32_t r = r0 + 1; r < r1; ++r) {
+    if (rule_applies(load_rule<RB>(s, r), n)) {
       if (j == 0) return r;
       --j;
     }
@@ -129,36 +175,71 @@ __device__ __forceinline__ bool step_prologue(const SysDev& s, int32_t j, int64_
   return true;
 }
 
-// Selection + delay bookkeeping of neuron i holding C spikes (C_k) with meta
-// word `meta` (D_k).  Writes the neuron's state and returns the spikes that
-// leave it at this step and the rule slot that sends them.
+// What a neuron needs to take its step, loaded ahead of its use.
+struct NeuronIn {
+  int32_t C;        // C_k (after reception)
+  uint32_t meta;    // D_k and reception flag
+  int32_t r0, r1;   // rule slots
+  int32_t pend;     // pending slot (STANDARD, D_k == 1)
+  Rule rec;         // open neuron: record of slot r0 (if r0 < r1);
+                    // neuron opening now (STANDARD): record of the pending slot
+};
+
+template <int RB>
+__device__ __forceinline__ void prefetch_neuron(const SysDev& s, int32_t i, uint32_t meta,
+                                                NeuronIn& in) {
+  in.meta = meta;
+  in.r0 = s.rs[i];
+  in.r1 = s.rs[i + 1];
+  const int32_t D = (int32_t)(meta & META_D);
+  in.pend = -1;
+  int32_t slot = -1;
+  if (D == 0) {
+    if (in.r0 < in.r1) slot = in.r0;
+  } else if (D == 1 && s.sem == SEM_STANDARD) {
+    in.pend = s.pend[i];
+    slot = in.pend;
+  }
+  if (slot >= 0) in.rec = load_rule<RB>(s, slot);
+}
+
+// Selection + delay bookkeeping of neuron i.  Writes the neuron's state and
+// returns the spikes that leave it at this step and the rule slot that sends
+// them.
 struct Sel {
   int32_t emit;   // spikes sent to every out-neighbour (0 = none)
   int32_t erule;  // slot of the rule whose spikes leave
   bool act;       // neuron is active in state k (closed, or has an applicable rule)
 };
 
-template <bool CNT>
-__device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k, int32_t C,
-                                             uint32_t meta, Cnt& cnt) {
-  const int32_t D = (int32_t)(meta & META_D);
-  const int32_t r0 = s.rs[i];
+template <int RB, bool CNT>
+__device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k,
+                                             const NeuronIn& in, Cnt& cnt) {
+  const int32_t D = (int32_t)(in.meta & META_D);
   int32_t Dn = 0, cons = 0, sel = -1;
   Sel o{0, -1, false};
   if (D == 0) {
-    const int32_t r1 = s.rs[i + 1];
-    sel = choose_rule(s, i, k, C, r0, r1);
+    sel = choose_rule<RB>(s, i, k, in.C, in.r0, in.r1, in.rec);
     if (CNT) {
       cnt.v[C_OPEN] += 1;
-      cnt.v[C_RULES] += (unsigned long long)(r1 - r0);
+      cnt.v[C_RULES] += (unsigned long long)(in.r1 - in.r0);
     }
     if (sel >= 0) {
-      const RuleRec r = s.rules[sel];
-      const int32_t p = (int32_t)(r.pd & 0xFFFFu), d = (int32_t)(r.pd >> 16);
-      cons = r.c;
-      Dn = d;
-      if (s.sem == SEM_PAPER || d == 0) {
-        o.emit = p;
+      int32_t rc, rp, rd;
+      if (sel == in.r0) {
+        rc = in.rec.c;
+        rp = in.rec.p;
+        rd = in.rec.d;
+      } else {
+        const Rule r = load_rule<RB>(s, sel);
+        rc = r.c;
+        rp = r.p;
+        rd = r.d;
+      }
+      cons = rc;
+      Dn = rd;
+      if (s.sem == SEM_PAPER || rd == 0) {
+        o.emit = rp;
         o.erule = sel;
       } else {
         s.pend[i] = sel;
@@ -171,15 +252,15 @@ __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t
     o.act = true;
     if (CNT && Dn == 0) cnt.v[C_REOPEN] += 1;
     if (s.sem == SEM_STANDARD && Dn == 0) {
-      o.erule = s.pend[i];
-      o.emit = (int32_t)(s.rules[o.erule].pd & 0xFFFFu);
+      o.erule = in.pend;
+      o.emit = in.rec.p;
     }
   }
   const uint32_t rf = (s.sem == SEM_PAPER) ? (D == 0 ? 1u : 0u) : (Dn == 0 ? 1u : 0u);
-  s.C[i] = C - cons;
+  s.C[i] = in.C - cons;
   const uint32_t nm = (uint32_t)Dn | (rf << 31);
-  if (nm != meta) s.meta[i] = nm;
-  s.S16[k & 1][i] = sel >= 0 ? (uint16_t)(sel - r0) : S_NONE;
+  if (nm != in.meta) s.meta[i] = nm;
+  pick(s.S16[0], s.S16[1], k)[i] = sel >= 0 ? (uint16_t)(sel - in.r0) : S_NONE;
   if (CNT && o.emit > 0) cnt.v[C_EMIT] += 1;
   return o;
 }
@@ -187,7 +268,7 @@ __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t
 // Caller id of the rule recorded for neuron i in S16[buf], or -1.
 __device__ __forceinline__ int32_t spiking_id(const SysDev& s, int32_t buf, int32_t i) {
   if (buf < 0) return -1;
-  const uint16_t x = s.S16[buf][i];
+  const uint16_t x = pick(s.S16[0], s.S16[1], buf)[i];
   return x == S_NONE ? -1 : s.rid[s.rs[i] + x];
 }
 
@@ -195,7 +276,7 @@ __device__ __forceinline__ int32_t spiking_id(const SysDev& s, int32_t buf, int3
 
 constexpr int PUSH_NT = 256;
 
-template <int LAYOUT, uint32_t FLAGS>
+template <int LAYOUT, int RB, uint32_t FLAGS>
 __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j) {
   constexpr bool DIG = (FLAGS & F_DIGEST) != 0;
   constexpr bool CNT = (FLAGS & F_COUNTERS) != 0;
@@ -208,13 +289,14 @@ __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j)
   unsigned long long dig = 0;
   Sel o{0, -1, false};
   if (i < s.q) {
+    NeuronIn in;
+    prefetch_neuron<RB>(s, i, s.meta[i], in);
     int32_t C = s.C[i];
-    const uint32_t meta = s.meta[i];
     if (k > 0) {
-      int32_t* prev = s.delta[(k - 1) & 1];
+      int32_t* prev = pick(s.delta[0], s.delta[1], k - 1);
       const int32_t recv = prev[i];
       if (recv != 0) prev[i] = 0;
-      if (meta & META_RECV) {
+      if (in.meta & META_RECV) {
         const uint32_t sum = (uint32_t)C + (uint32_t)recv;
         if ((int32_t)sum < 0) s.ctl->overflow = 1;
         C = (int32_t)sum;
@@ -226,16 +308,17 @@ __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j)
         cnt.v[C_LOST] += (unsigned long long)recv;
       }
     }
+    in.C = C;
     if (DIG && k > 0)
-      dig = digest_term(i, C, (int32_t)(meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), i));
-    o = select_update<CNT>(s, i, k, C, meta, cnt);
+      dig = digest_term(i, C, (int32_t)(in.meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), i));
+    o = select_update<RB, CNT>(s, i, k, in, cnt);
   }
   // state k is active if any neuron is
   const unsigned long long am = __ballot(o.act);
   if (am && (threadIdx.x & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;
 
   if (o.emit > 0) {
-    int32_t* cur = s.delta[k & 1];
+    int32_t* cur = pick(s.delta[0], s.delta[1], k);
     int32_t deg = 0;
     if (LAYOUT == L_OPT) {
       for (int32_t r = 0; r < s.z; ++r) {
@@ -275,86 +358,120 @@ __global__ void __launch_bounds__(PUSH_NT) step_push_kernel(SysDev s, int32_t j)
 
 // ------------------------------------------------------------ pull step --
 
-constexpr int PULL_NT = 512;    // threads per block
-constexpr int PULL_NPT = 4;     // targets per thread
-constexpr int PULL_TILE = PULL_NT * PULL_NPT;
+constexpr int PULL_NPT = 4;              // neurons per thread
 
-// Each block owns PULL_TILE consecutive neurons.  Reception of step k-1: the
-// packed emit vector of step k-1 is staged chunk by chunk in LDS; every
-// thread walks the in-neighbour lists of its neurons (sorted by source) and
-// sums the values of the current chunk.  Then selection and delays, and the
-// block packs its neurons' emitted values into the emit vector of step k.
-template <int W, uint32_t FLAGS>
-__global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j) {
+// Each block owns 2^TB consecutive neurons (4 per thread).  Reception of step
+// k-1: the in-edges of the tile are stored per source chunk as u32 records
+// (source offset in the chunk << TB | target offset in the tile), each
+// segment padded to a multiple of 4 records with 0xFFFFFFFF.  For every
+// chunk the block stages the chunk's packed emitted values (W bits per
+// neuron) in LDS, streams its edge records 16 bytes per lane and adds each
+// value into an LDS accumulator of the target.  Then selection and delays
+// per neuron, and the block packs its neurons' emitted values into the emit
+// vector of step k.  Rule offsets and the first rule record of every neuron
+// are loaded before the reception so that their latency overlaps it.
+template <int TB, int W, int RB, uint32_t FLAGS>
+__global__ void __launch_bounds__((1 << TB) / PULL_NPT) step_pull_kernel(SysDev s, int32_t j) {
+  constexpr int PULL_TILE = 1 << TB;
+  constexpr int PULL_NT = PULL_TILE / PULL_NPT;
+  constexpr int PULL_TBITS = TB;
   constexpr bool DIG = (FLAGS & F_DIGEST) != 0;
   constexpr bool CNT = (FLAGS & F_COUNTERS) != 0;
-  constexpr uint32_t VMASK = (W == 32) ? 0xFFFFFFFFu : ((1u << W) - 1u);
+  constexpr uint32_t VMASK = (1u << W) - 1u;
   constexpr int TILE_WORDS = PULL_TILE * W / 32;
-  extern __shared__ uint32_t lds[];
-  uint32_t* stage = lds;                     // [TILE_WORDS] emit values of this tile
-  uint32_t* chunk = lds + TILE_WORDS;        // [pull_chunk * W / 32]
+  extern __shared__ uint4 lds4[];
+  uint32_t* lds = (uint32_t*)lds4;
+  int32_t* acc = (int32_t*)lds;              // [PULL_TILE] spikes received by each neuron
+  uint32_t* stage = lds + PULL_TILE;         // [TILE_WORDS] emitted values of this tile
+  uint32_t* chunk = stage + TILE_WORDS;      // emitted values of one source chunk (16-byte aligned)
   __shared__ unsigned long long red[PULL_NT / 64];
   int64_t k;
   if (!step_prologue(s, j, k)) return;
   const int32_t t0 = blockIdx.x * PULL_TILE;
   const int tid = threadIdx.x;
 
-  int32_t e[PULL_NPT], eend[PULL_NPT], recv[PULL_NPT], nsrc[PULL_NPT];
-  uint32_t meta[PULL_NPT];
+  NeuronIn in[PULL_NPT];
+#pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
     const int32_t t = t0 + tid + r * PULL_NT;
-    recv[r] = 0;
-    e[r] = eend[r] = 0;
-    nsrc[r] = 0x7FFFFFFF;
-    meta[r] = 0;
+    in[r].C = 0;
     if (t < s.q) {
-      meta[r] = s.meta[t];
-      if (k > 0 && (CNT || (meta[r] & META_RECV))) {
-        e[r] = s.in_ptr[t];
-        eend[r] = s.in_ptr[t + 1];
-        if (e[r] < eend[r]) nsrc[r] = s.in_src[e[r]];
-      }
+      in[r].C = s.C[t];
+      prefetch_neuron<RB>(s, t, s.meta[t], in[r]);
+    } else {
+      in[r].meta = 0;
     }
+    acc[tid + r * PULL_NT] = 0;
   }
   for (int w = tid; w < TILE_WORDS; w += PULL_NT) stage[w] = 0u;
 
   if (k > 0) {
-    const uint32_t* ebuf = s.emit[(k - 1) & 1];
+    const uint32_t* ebuf = pick(s.emit[0], s.emit[1], k - 1);
+    const int32_t* seg = s.pseg + (size_t)blockIdx.x * s.pull_nc;
     const int32_t csz = s.pull_chunk;
-    for (int32_t c0 = 0; c0 < s.q; c0 += csz) {
-      const int32_t c1 = min(s.q, c0 + csz);
-      // skip chunks no neuron of this block reads from
-      int32_t mymin = 0x7FFFFFFF;
-      for (int r = 0; r < PULL_NPT; ++r) mymin = min(mymin, nsrc[r]);
-      const int need = __syncthreads_or(mymin < c1 ? 1 : 0);
-      if (!need) continue;
+    const uint4* pe4 = reinterpret_cast<const uint4*>(s.pedge);
+    for (int32_t c = 0; c < s.pull_nc; ++c) {
+      const int32_t e0 = seg[c], e1 = seg[c + 1];
+      if (e0 == e1) continue;
+      const int32_t c0 = c * csz, c1 = min(s.q, c0 + csz);
+      // words [w0, w0 + 4*nv) of the emit vector; w0 is a multiple of 4
       const int32_t w0 = (int32_t)(((int64_t)c0 * W) >> 5);
-      const int32_t nw = (int32_t)((((int64_t)(c1 - c0)) * W + 31) >> 5);
-      for (int32_t w = tid; w < nw; w += PULL_NT) chunk[w] = ebuf[w0 + w];
-      __syncthreads();
-      for (int r = 0; r < PULL_NPT; ++r) {
-        while (nsrc[r] < c1) {
-          const uint32_t off = (uint32_t)(nsrc[r] - c0) * W;
-          recv[r] += (int32_t)((chunk[off >> 5] >> (off & 31)) & VMASK);
-          ++e[r];
-          nsrc[r] = (e[r] < eend[r]) ? s.in_src[e[r]] : 0x7FFFFFFF;
-        }
+      const int32_t nv = (int32_t)(((((int64_t)(c1 - c0)) * W + 31) >> 5) + 3) >> 2;
+      const uint4* src4 = reinterpret_cast<const uint4*>(ebuf + w0);
+      uint4* dst4 = reinterpret_cast<uint4*>(chunk);
+      __syncthreads();  // readers of the previous chunk are done
+      for (int32_t v = tid; v < nv; v += 4 * PULL_NT) {
+        // four 16-byte loads in flight per lane; indexes past the end are
+        // clamped to the last group and their copies skipped
+        uint4 a0 = src4[min(v, nv - 1)];
+        uint4 a1 = src4[min(v + PULL_NT, nv - 1)];
+        uint4 a2 = src4[min(v + 2 * PULL_NT, nv - 1)];
+        uint4 a3 = src4[min(v + 3 * PULL_NT, nv - 1)];
+        dst4[v] = a0;
+        if (v + PULL_NT < nv) dst4[v + PULL_NT] = a1;
+        if (v + 2 * PULL_NT < nv) dst4[v + 2 * PULL_NT] = a2;
+        if (v + 3 * PULL_NT < nv) dst4[v + 3 * PULL_NT] = a3;
       }
       __syncthreads();
+      const int32_t v0 = e0 >> 2, v1 = e1 >> 2;
+      for (int32_t v = v0 + tid; v < v1; v += 4 * PULL_NT) {
+        uint4 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t vu = v + u * PULL_NT;
+          const uint4 y = pe4[min(vu, v1 - 1)];
+          x[u] = vu < v1 ? y : make_uint4(~0u, ~0u, ~0u, ~0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            if (xs[h] == 0xFFFFFFFFu) continue;
+            const uint32_t bit = (xs[h] >> PULL_TBITS) * W;
+            const uint32_t val = (chunk[bit >> 5] >> (bit & 31)) & VMASK;
+            if (val) atomicAdd(&acc[xs[h] & (PULL_TILE - 1)], (int32_t)val);
+          }
+        }
+      }
     }
   }
+  __syncthreads();
 
   Cnt cnt;
   cnt.zero();
   unsigned long long dig = 0;
   bool anyact = false;
+#pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
-    const int32_t t = t0 + tid + r * PULL_NT;
+    const int32_t lt = tid + r * PULL_NT;
+    const int32_t t = t0 + lt;
     if (t >= s.q) continue;
-    int32_t C = s.C[t];
+    int32_t C = in[r].C;
     if (k > 0) {
-      if (meta[r] & META_RECV) {
-        const uint32_t sum = (uint32_t)C + (uint32_t)recv[r];
+      const int32_t got = acc[lt];
+      if (in[r].meta & META_RECV) {
+        const uint32_t sum = (uint32_t)C + (uint32_t)got;
         if ((int32_t)sum < 0) s.ctl->overflow = 1;
         C = (int32_t)sum;
         if (CNT) {
@@ -362,15 +479,16 @@ __global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j)
           cnt.v[C_INEDGES] += (unsigned long long)(s.in_ptr[t + 1] - s.in_ptr[t]);
         }
       } else if (CNT) {
-        cnt.v[C_LOST] += (unsigned long long)recv[r];
+        cnt.v[C_LOST] += (unsigned long long)got;
       }
     }
+    in[r].C = C;
     if (DIG && k > 0)
-      dig += digest_term(t, C, (int32_t)(meta[r] & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
-    const Sel o = select_update<CNT>(s, t, k, C, meta[r], cnt);
+      dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
+    const Sel o = select_update<RB, CNT>(s, t, k, in[r], cnt);
     anyact |= o.act;
     if (o.emit > 0) {
-      const uint32_t off = (uint32_t)(t - t0) * W;
+      const uint32_t off = (uint32_t)lt * W;
       atomicOr(&stage[off >> 5], ((uint32_t)o.emit & VMASK) << (off & 31));
       if (CNT) {
         const unsigned long long dg = (unsigned long long)s.out_deg[t];
@@ -382,7 +500,7 @@ __global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j)
   const unsigned long long am = __ballot(anyact);
   if (am && (tid & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;
   __syncthreads();
-  uint32_t* enext = s.emit[k & 1] + (size_t)blockIdx.x * TILE_WORDS;
+  uint32_t* enext = pick(s.emit[0], s.emit[1], k) + (size_t)blockIdx.x * TILE_WORDS;
   for (int w = tid; w < TILE_WORDS; w += PULL_NT) enext[w] = stage[w];
 
   if (DIG && k > 0) block_add64<PULL_NT>(dig, (unsigned long long*)&s.digests[(k - 1) % s.ring], red);
@@ -397,46 +515,83 @@ __global__ void __launch_bounds__(PULL_NT) step_pull_kernel(SysDev s, int32_t j)
   }
 }
 
-int pull_threads() { return PULL_NT; }
-int pull_tile() { return PULL_TILE; }
 size_t pull_lds_bytes(const SysDev& s) {
-  return (size_t)(PULL_TILE * s.emit_w / 32) * 4 + (((size_t)s.pull_chunk * s.emit_w + 31) / 32) * 4;
+  const int64_t tile = 1LL << s.pull_tb;
+  const int64_t csz = std::min<int64_t>(s.pull_chunk, ((int64_t)s.q + 127) / 128 * 128);
+  const int64_t cwords = ((csz * s.emit_w + 31) / 32 + 3) / 4 * 4;
+  return (size_t)(tile * 4 + tile * s.emit_w / 32 * 4 + cwords * 4);
+}
+
+// Lets the pull kernels use up to `bytes` of dynamic LDS.
+hipError_t prepare_pull_kernels(size_t bytes) {
+  hipError_t e = hipSuccess;
+#define SNP_SET_LDS(TT, WW, RR, FL)                                                           \
+  if (e == hipSuccess)                                                                        \
+    e = hipFuncSetAttribute((const void*)step_pull_kernel<TT, WW, RR, FL>,                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+#define SNP_SET_LDS_R(TT, WW, RR)                                                       \
+  SNP_SET_LDS(TT, WW, RR, 0u) SNP_SET_LDS(TT, WW, RR, F_DIGEST) SNP_SET_LDS(TT, WW, RR, F_COUNTERS) \
+  SNP_SET_LDS(TT, WW, RR, F_DIGEST | F_COUNTERS)
+#define SNP_SET_LDS_W(TT, WW) SNP_SET_LDS_R(TT, WW, 8) SNP_SET_LDS_R(TT, WW, 16)
+#define SNP_SET_LDS_T(TT) \
+  SNP_SET_LDS_W(TT, 1) SNP_SET_LDS_W(TT, 2) SNP_SET_LDS_W(TT, 4) SNP_SET_LDS_W(TT, 8) SNP_SET_LDS_W(TT, 16)
+  SNP_SET_LDS_T(11) SNP_SET_LDS_T(12)
+#undef SNP_SET_LDS_T
+#undef SNP_SET_LDS_W
+#undef SNP_SET_LDS_R
+#undef SNP_SET_LDS
+  return e;
 }
 
 // ------------------------------------------------------------- dispatch --
 
-template <uint32_t FL>
-static hipError_t launch_step_fl(const SysDev& s, int32_t j, hipStream_t st) {
+template <int RB, uint32_t FL>
+static hipError_t launch_step_rf(const SysDev& s, int32_t j, hipStream_t st) {
   if (s.layout == L_CSR_PULL) {
-    const dim3 grid((s.q + PULL_TILE - 1) / PULL_TILE);
+    const int tile = 1 << s.pull_tb, nt = tile / PULL_NPT;
+    const dim3 grid((s.q + tile - 1) / tile);
     const size_t lds = pull_lds_bytes(s);
-    switch (s.emit_w) {
-      case 1: step_pull_kernel<1, FL><<<grid, PULL_NT, lds, st>>>(s, j); break;
-      case 2: step_pull_kernel<2, FL><<<grid, PULL_NT, lds, st>>>(s, j); break;
-      case 4: step_pull_kernel<4, FL><<<grid, PULL_NT, lds, st>>>(s, j); break;
-      case 8: step_pull_kernel<8, FL><<<grid, PULL_NT, lds, st>>>(s, j); break;
-      case 16: step_pull_kernel<16, FL><<<grid, PULL_NT, lds, st>>>(s, j); break;
-      default: return hipErrorInvalidValue;
+#define SNP_PULL_W(TT)                                                                        \
+  switch (s.emit_w) {                                                                         \
+    case 1: step_pull_kernel<TT, 1, RB, FL><<<grid, nt, lds, st>>>(s, j); break;              \
+    case 2: step_pull_kernel<TT, 2, RB, FL><<<grid, nt, lds, st>>>(s, j); break;              \
+    case 4: step_pull_kernel<TT, 4, RB, FL><<<grid, nt, lds, st>>>(s, j); break;              \
+    case 8: step_pull_kernel<TT, 8, RB, FL><<<grid, nt, lds, st>>>(s, j); break;              \
+    case 16: step_pull_kernel<TT, 16, RB, FL><<<grid, nt, lds, st>>>(s, j); break;            \
+    default: return hipErrorInvalidValue;                                                     \
+  }
+    if (s.pull_tb == 12) {
+      SNP_PULL_W(12)
+    } else if (s.pull_tb == 11) {
+      SNP_PULL_W(11)
+    } else {
+      return hipErrorInvalidValue;
     }
+#undef SNP_PULL_W
     return hipGetLastError();
   }
   const dim3 grid((s.q + PUSH_NT - 1) / PUSH_NT);
   switch (s.layout) {
-    case L_OPT: step_push_kernel<L_OPT, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
-    case L_ELL: step_push_kernel<L_ELL, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
-    case L_CSR_PUSH: step_push_kernel<L_CSR_PUSH, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
+    case L_OPT: step_push_kernel<L_OPT, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
+    case L_ELL: step_push_kernel<L_ELL, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
+    case L_CSR_PUSH: step_push_kernel<L_CSR_PUSH, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st) {
+template <int RB>
+static hipError_t launch_step_r(const SysDev& s, int32_t j, hipStream_t st) {
   switch (s.flags & (F_DIGEST | F_COUNTERS)) {
-    case 0: return launch_step_fl<0>(s, j, st);
-    case F_DIGEST: return launch_step_fl<F_DIGEST>(s, j, st);
-    case F_COUNTERS: return launch_step_fl<F_COUNTERS>(s, j, st);
-    default: return launch_step_fl<F_DIGEST | F_COUNTERS>(s, j, st);
+    case 0: return launch_step_rf<RB, 0>(s, j, st);
+    case F_DIGEST: return launch_step_rf<RB, F_DIGEST>(s, j, st);
+    case F_COUNTERS: return launch_step_rf<RB, F_COUNTERS>(s, j, st);
+    default: return launch_step_rf<RB, F_DIGEST | F_COUNTERS>(s, j, st);
   }
+}
+
+hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st) {
+  return s.rule_bytes == 8 ? launch_step_r<8>(s, j, st) : launch_step_r<16>(s, j, st);
 }
 
 __global__ void advance_kernel(Ctl* ctl, int32_t n) {
@@ -461,9 +616,9 @@ __global__ void materialize_kernel(SysDev s, int32_t rbuf, int32_t sbuf, int32_t
   int32_t C = s.C[i];
   if (rbuf >= 0 && (meta & META_RECV)) {
     if (s.layout == L_CSR_PULL) {
-      const uint32_t* eb = s.emit[rbuf];
+      const uint32_t* eb = pick(s.emit[0], s.emit[1], rbuf);
       const uint32_t W = (uint32_t)s.emit_w;
-      const uint32_t mask = (W == 32) ? 0xFFFFFFFFu : ((1u << W) - 1u);
+      const uint32_t mask = (1u << W) - 1u;
       int32_t acc = 0;
       for (int32_t e = s.in_ptr[i]; e < s.in_ptr[i + 1]; ++e) {
         const uint64_t off = (uint64_t)(uint32_t)s.in_src[e] * W;
@@ -471,7 +626,7 @@ __global__ void materialize_kernel(SysDev s, int32_t rbuf, int32_t sbuf, int32_t
       }
       C = (int32_t)((uint32_t)C + (uint32_t)acc);
     } else {
-      C = (int32_t)((uint32_t)C + (uint32_t)s.delta[rbuf][i]);
+      C = (int32_t)((uint32_t)C + (uint32_t)pick(s.delta[0], s.delta[1], rbuf)[i]);
     }
     if (C < 0) s.ctl->overflow = 1;  // the pending reception left the int32 range
   }
@@ -507,6 +662,7 @@ hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, i
 
 // Is the (materialized) state active: some neuron closed, or some open
 // neuron with an applicable rule?  *out must be 0 on entry.
+template <int RB>
 __global__ void activity_kernel(SysDev s, const int32_t* C, const int32_t* D, int32_t* out) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   bool act = false;
@@ -514,7 +670,8 @@ __global__ void activity_kernel(SysDev s, const int32_t* C, const int32_t* D, in
     if (D[i] > 0) {
       act = true;
     } else {
-      for (int32_t r = s.rs[i]; r < s.rs[i + 1] && !act; ++r) act = rule_applies(s.rules[r], C[i]);
+      for (int32_t r = s.rs[i]; r < s.rs[i + 1] && !act; ++r)
+        act = rule_applies(load_rule<RB>(s, r), C[i]);
     }
   }
   const unsigned long long am = __ballot(act);
@@ -523,7 +680,8 @@ __global__ void activity_kernel(SysDev s, const int32_t* C, const int32_t* D, in
 
 hipError_t launch_activity(const SysDev& s, const int32_t* C, const int32_t* D, int32_t* out,
                            hipStream_t st) {
-  activity_kernel<<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
+  if (s.rule_bytes == 8) activity_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
+  else activity_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
   return hipGetLastError();
 }
 
@@ -538,15 +696,15 @@ __global__ void recv_counts_kernel(SysDev s, int32_t rbuf, unsigned long long* o
     const uint32_t meta = s.meta[i];
     int32_t got = 0;
     if (s.layout == L_CSR_PULL) {
-      const uint32_t* eb = s.emit[rbuf];
+      const uint32_t* eb = pick(s.emit[0], s.emit[1], rbuf);
       const uint32_t W = (uint32_t)s.emit_w;
-      const uint32_t mask = (W == 32) ? 0xFFFFFFFFu : ((1u << W) - 1u);
+      const uint32_t mask = (1u << W) - 1u;
       for (int32_t e = s.in_ptr[i]; e < s.in_ptr[i + 1]; ++e) {
         const uint64_t off = (uint64_t)(uint32_t)s.in_src[e] * W;
         got += (int32_t)((eb[off >> 5] >> (off & 31)) & mask);
       }
     } else {
-      got = s.delta[rbuf][i];
+      got = pick(s.delta[0], s.delta[1], rbuf)[i];
     }
     if (meta & META_RECV) {
       recv = 1;
@@ -585,23 +743,24 @@ hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st) {
 // ELL (Table 2): column of rule slot r of neuron i: row 0 = (i, -c), rows
 // 1..deg = (target, +p) for p > 0, the rest (-1, 0); stored row-major
 // [z+1][m] so that a row is contiguous over rules.
+template <int RB>
 __global__ void build_ell_kernel(SysDev s, int2* ell) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.q) return;
   const int32_t e0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - e0;
   for (int32_t r = s.rs[i]; r < s.rs[i + 1]; ++r) {
-    const RuleRec rr = s.rules[r];
-    const int32_t p = (int32_t)(rr.pd & 0xFFFFu);
+    const Rule rr = load_rule<RB>(s, r);
     ell[r] = make_int2(i, -rr.c);
     for (int32_t row = 1; row <= s.z; ++row) {
-      const bool on = p > 0 && row <= deg;
-      ell[(int64_t)row * s.m + r] = on ? make_int2(s.out_col[e0 + row - 1], p) : make_int2(-1, 0);
+      const bool on = rr.p > 0 && row <= deg;
+      ell[(int64_t)row * s.m + r] = on ? make_int2(s.out_col[e0 + row - 1], rr.p) : make_int2(-1, 0);
     }
   }
 }
 
 hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st) {
-  build_ell_kernel<<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
+  if (s.rule_bytes == 8) build_ell_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
+  else build_ell_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
   return hipGetLastError();
 }
 
@@ -614,7 +773,7 @@ __global__ void restore_kernel(SysDev s, int32_t sbuf, const int32_t* C, const i
   s.C[i] = C[i];
   s.meta[i] = (uint32_t)D[i] | META_RECV;
   s.pend[i] = (P && P[i] >= 0) ? slot_of[P[i]] : -1;
-  if (sbuf >= 0) s.S16[sbuf][i] = (S && S[i] >= 0) ? (uint16_t)(slot_of[S[i]] - s.rs[i]) : S_NONE;
+  if (sbuf >= 0) pick(s.S16[0], s.S16[1], sbuf)[i] = (S && S[i] >= 0) ? (uint16_t)(slot_of[S[i]] - s.rs[i]) : S_NONE;
 }
 
 hipError_t launch_restore(const SysDev& s, int32_t sbuf, const int32_t* C, const int32_t* D,

@@ -70,6 +70,24 @@ def test_hash_ragged_sizes_every_step(binding, layout, q):
         compare_every_step(binding, spec, layout, sem_name, sem, 25)
 
 
+@pytest.mark.parametrize("q", [2047, 2048, 2049, 6001])
+def test_pull_small_tile_every_step(binding, q):
+    # 2048-neuron tiles (two blocks per compute unit) on ragged sizes
+    spec = wl.small_random(q + 5, q, max_deg=9, max_rules=4, dmax=3, c0max=8,
+                           select=wl.SELECT_HASH, steps=25)
+    for sem_name, sem in SEMS:
+        compare_every_step(binding, spec, "csr_pull", sem_name, sem, 25, pull_tile_log2=11)
+
+
+def test_pull_small_tile_several_chunks(binding):
+    spec = wl.config2(q=700_000, steps=15)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(15, want_state=False)
+    g = binding.System.from_spec(spec, layout="csr_pull", digest=True, pull_tile_log2=11)
+    assert g.info()["pull_chunks"] >= 2
+    g.step(15)
+    assert np.array_equal(g.read_digests(0, 15), ref["digests"])
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_hand_trace_h1(binding, layout):
     rules = np.array([(0, 1, 0, 1, 1, 2), (1, 1, 0, 1, 1, 0)], np.int32)
@@ -184,6 +202,18 @@ def test_pull_emit_widths(binding, W, pmax):
     spec.rules[:, 4] = rng.integers(0, pmax + 1, size=spec.m)
     spec.rules[0, 4] = pmax
     compare_every_step(binding, spec, "csr_pull", "standard", orc.SEM_STANDARD, 15)
+
+
+def test_pull_wide_values_several_chunks(binding):
+    # 16-bit emitted values: about 68k sources per LDS chunk, so 150k neurons span 3 chunks
+    rng = np.random.default_rng(3)
+    spec = wl.small_random(4242, 150_000, max_deg=12, max_rules=3, dmax=3, c0max=8,
+                           select=wl.SELECT_HASH)
+    spec.rules[:, 4] = rng.integers(0, 40000, size=spec.m)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(12, want_state=False)
+    g = binding.System.from_spec(spec, layout="csr_pull", digest=True)
+    g.step(12)
+    assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"])
 
 
 def test_pull_several_lds_chunks(binding):
