@@ -56,10 +56,10 @@ def step_bytes(layout, q, c, info):
     return state_bytes(q, c, info["rule_bytes"]) + layout_bytes(layout, q, c, info["emit_bits"])
 
 
-def run_layout(binding, torch, spec, layout, steps, warmup, chunk, tile_log2):
+def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
     """Times `steps` steps after `warmup` on one system; returns a result dict."""
     t0 = time.time()
-    g = binding.System.from_spec(spec, layout=layout, chunk=chunk, pull_tile_log2=tile_log2)
+    g = binding.System.from_spec(spec, layout=layout, chunk=chunk)
     create_s = time.time() - t0
     info = g.info()
     stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
@@ -122,7 +122,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--q", type=int, default=1 << 20)
-    ap.add_argument("--pull-tile-log2", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator is a single-GPU build "
@@ -143,8 +142,7 @@ def main():
         layouts.insert(0, args.layout)
     results = {}
     for lay in layouts:
-        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk,
-                       args.pull_tile_log2)
+        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk)
         if not args.no_counters:
             b, cnt = count_bytes(binding, spec, lay, args.steps, args.warmup, r["info"])
             r["alg_bytes_per_step"] = b

@@ -85,6 +85,7 @@ extern "C" {
 #define SNP_F_DIGEST   0x1u /* keep a digest of every reached state          */
 #define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
 #define SNP_F_NO_GRAPH 0x4u /* launch step kernels one by one (no hipGraph)  */
+#define SNP_F_WIDE_RULES 0x8u /* keep 16-byte rule records even when 8 fit  */
 
 /* Device memory hooks (e.g. a framework's caching allocator).  `stream` is
  * the handle's hipStream_t.  NULL hooks = hipMalloc / hipFree.            */
@@ -102,8 +103,8 @@ typedef struct snp_opts {
   uint32_t flags;      /* SNP_F_*                                            */
   int32_t device;      /* HIP device ordinal; -1 = current device            */
   int64_t ring;        /* entries kept by the digest / counter rings; 0 = 4096 */
-  int32_t pull_tile_log2; /* CSR_PULL: log2 of the neurons one block owns, 11
-                             (two blocks per compute unit) or 12 (one); 0 = 12 */
+  int32_t emit_bits;   /* CSR_PULL: bits per emitted value (1, 2, 4, 8, 16);
+                          0 = the smallest that holds every p               */
   snp_alloc_fn alloc;
   snp_free_fn free;
   void* alloc_ctx;
@@ -251,6 +252,51 @@ int snp_destroy(snp_sys* sys);
 
 /* hipStream_t the handle runs on. */
 void* snp_stream(snp_sys* sys);
+
+/* Step limit L: steps with index >= L are not executed (Alg. 1 stops at
+ * k = L), so the system stops after L executed steps even if more are
+ * enqueued.  limit < 0 removes the limit.  Waits for the handle's stream.  */
+int snp_set_step_limit(snp_sys* sys, int64_t limit);
+
+/* ---- batched form ------------------------------------------------------
+ * Many independent systems advanced together: one launch per step covers
+ * every tile of every member, each member keeps its own step index, HASH
+ * key, halting flag and step limit, so a member's computation is the same
+ * as when it runs alone.  Members must share layout, rule record size,
+ * emit width, pull tile size and SNP_F_DIGEST / SNP_F_COUNTERS flags
+ * (SNP_ENOTSUP otherwise).  While in a batch a handle refuses snp_step,
+ * snp_write_state and snp_destroy (SNP_EBUSY); its read calls work.      */
+typedef struct snp_batch snp_batch;
+
+typedef struct snp_batch_opts {
+  int32_t chunk;            /* steps per captured graph; 0 = 64              */
+  int32_t capacity_members; /* initial room; grows on demand; 0 = 256        */
+  int32_t capacity_tiles;   /* initial room in blocks; grows; 0 = 4096       */
+  int32_t pad;
+  void* stream;             /* hipStream_t; NULL = the library creates one   */
+} snp_batch_opts;
+
+void snp_batch_opts_default(snp_batch_opts* opts);
+
+/* Creates a batch of the n handles (n may be 0). */
+int snp_batch_create(int32_t n, snp_sys* const* systems, const snp_batch_opts* opts,
+                     snp_batch** out);
+/* Adds / removes one member (waits for the streams involved). */
+int snp_batch_add(snp_batch* b, snp_sys* sys);
+int snp_batch_remove(snp_batch* b, snp_sys* sys);
+/* Enqueues k steps of every member on the batch stream; returns at once. */
+int snp_batch_step(snp_batch* b, int64_t k);
+/* Waits for the batch stream. */
+int snp_batch_sync(snp_batch* b);
+/* Member count and blocks per step launch. */
+int snp_batch_size(snp_batch* b, int32_t* members, int32_t* tiles);
+/* Members in their current order (host [capacity] of handles). */
+int snp_batch_members(snp_batch* b, snp_sys** out, int32_t capacity);
+/* Waits, then per member (current order): executed steps, and done = 1 if
+ * the member halted or reached its step limit (host [members] each).     */
+int snp_batch_status(snp_batch* b, int64_t* steps, int32_t* done);
+/* Frees the batch (waits for it); the member handles stay valid. */
+int snp_batch_destroy(snp_batch* b);
 
 /* Text of a status code / of the last error on this thread. */
 const char* snp_strerror(int status);

@@ -19,7 +19,7 @@ from . import build as _build
 LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL = 0, 1, 2, 3, 4
 SELECT_FIRST, SELECT_HASH = 0, 1
 SEM_STANDARD, SEM_PAPER_KERNEL = 0, 1
-F_DIGEST, F_COUNTERS, F_NO_GRAPH = 0x1, 0x2, 0x4
+F_DIGEST, F_COUNTERS, F_NO_GRAPH, F_WIDE_RULES = 0x1, 0x2, 0x4, 0x8
 
 LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL,
            "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL}
@@ -31,7 +31,10 @@ SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_
            "snp_read_spiking", "snp_read_delays", "snp_read_pending", "snp_digest",
            "snp_read_digests", "snp_read_counters", "snp_write_state", "snp_read_layout",
            "snp_info", "snp_footprint", "snp_paper_sizes", "snp_destroy", "snp_stream",
-           "snp_strerror", "snp_last_error"]
+           "snp_strerror", "snp_last_error", "snp_set_step_limit", "snp_batch_opts_default",
+           "snp_batch_create", "snp_batch_add", "snp_batch_remove", "snp_batch_step",
+           "snp_batch_sync", "snp_batch_size", "snp_batch_members", "snp_batch_status",
+           "snp_batch_destroy"]
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
@@ -41,7 +44,7 @@ class Opts(ct.Structure):
     _fields_ = [("layout", ct.c_int32), ("select", ct.c_int32), ("semantics", ct.c_int32),
                 ("chunk", ct.c_int32), ("seed", ct.c_uint64), ("stream", ct.c_void_p),
                 ("flags", ct.c_uint32), ("device", ct.c_int32), ("ring", ct.c_int64),
-                ("pull_tile_log2", ct.c_int32),
+                ("emit_bits", ct.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ct.c_void_p)]
 
 
@@ -56,6 +59,11 @@ COUNTER_FIELDS = ["open_neurons", "rules_of_open", "selecting", "emitting", "emi
 
 class Counters(ct.Structure):
     _fields_ = [(n, ct.c_int64) for n in COUNTER_FIELDS]
+
+
+class BatchOpts(ct.Structure):
+    _fields_ = [("chunk", ct.c_int32), ("capacity_members", ct.c_int32),
+                ("capacity_tiles", ct.c_int32), ("pad", ct.c_int32), ("stream", ct.c_void_p)]
 
 
 class Info(ct.Structure):
@@ -102,6 +110,17 @@ def _load():
         "snp_stream": (vp, [vp]),
         "snp_strerror": (ct.c_char_p, [ct.c_int]),
         "snp_last_error": (ct.c_char_p, []),
+        "snp_set_step_limit": (ct.c_int, [vp, ct.c_int64]),
+        "snp_batch_opts_default": (None, [P(BatchOpts)]),
+        "snp_batch_create": (ct.c_int, [ct.c_int32, P(vp), P(BatchOpts), P(vp)]),
+        "snp_batch_add": (ct.c_int, [vp, vp]),
+        "snp_batch_remove": (ct.c_int, [vp, vp]),
+        "snp_batch_step": (ct.c_int, [vp, ct.c_int64]),
+        "snp_batch_sync": (ct.c_int, [vp]),
+        "snp_batch_size": (ct.c_int, [vp, i32p, i32p]),
+        "snp_batch_members": (ct.c_int, [vp, P(vp), ct.c_int32]),
+        "snp_batch_status": (ct.c_int, [vp, i64p, i32p]),
+        "snp_batch_destroy": (ct.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -180,7 +199,8 @@ class System:
 
     def __init__(self, q, spikes0, rules, src, dst, *, layout="auto", select="first",
                  semantics="standard", seed=0, chunk=64, digest=False, counters=False,
-                 graph=True, ring=0, device=None, memory="auto", stream=None, pull_tile_log2=0):
+                 graph=True, ring=0, device=None, memory="auto", stream=None, emit_bits=0,
+                 wide_rules=False):
         self._h = ct.c_void_p()
         self.q = int(q)
         s0 = _i32(spikes0)
@@ -196,9 +216,10 @@ class System:
         o.semantics = SEMANTICS[semantics] if isinstance(semantics, str) else int(semantics)
         o.chunk = int(chunk)
         o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
-        o.flags = (F_DIGEST if digest else 0) | (F_COUNTERS if counters else 0) | (0 if graph else F_NO_GRAPH)
+        o.flags = ((F_DIGEST if digest else 0) | (F_COUNTERS if counters else 0) |
+                   (0 if graph else F_NO_GRAPH) | (F_WIDE_RULES if wide_rules else 0))
         o.ring = int(ring)
-        o.pull_tile_log2 = int(pull_tile_log2)
+        o.emit_bits = int(emit_bits)
         o.device = -1 if device is None else int(device)
         torch = _torch_cuda()
         self._torch_stream = None
@@ -316,3 +337,87 @@ class System:
         i = Info()
         _check(lib.snp_info(self._h, ct.byref(i)))
         return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "pad"}
+
+    def set_step_limit(self, limit):
+        _check(lib.snp_set_step_limit(self._h, -1 if limit is None else int(limit)))
+
+
+class Batch:
+    """Many systems advanced together by one launch per step (wraps ``snp_batch``)."""
+
+    def __init__(self, systems=(), *, chunk=64, capacity_members=0, capacity_tiles=0,
+                 stream=None):
+        self._h = ct.c_void_p()
+        self._members = {}
+        o = BatchOpts()
+        lib.snp_batch_opts_default(ct.byref(o))
+        o.chunk = int(chunk)
+        if capacity_members:
+            o.capacity_members = int(capacity_members)
+        if capacity_tiles:
+            o.capacity_tiles = int(capacity_tiles)
+        self._torch_stream = None
+        if stream is not None:
+            o.stream = int(stream)
+        else:
+            torch = _torch_cuda()
+            if torch is not None:
+                self._torch_stream = torch.cuda.Stream()
+                o.stream = self._torch_stream.cuda_stream
+        systems = list(systems)
+        arr = (ct.c_void_p * max(1, len(systems)))(*[x.handle.value for x in systems])
+        _check(lib.snp_batch_create(len(systems), arr, ct.byref(o), ct.byref(self._h)))
+        for x in systems:
+            self._members[x.handle.value] = x
+
+    def add(self, system):
+        _check(lib.snp_batch_add(self._h, system.handle))
+        self._members[system.handle.value] = system
+
+    def remove(self, system):
+        _check(lib.snp_batch_remove(self._h, system.handle))
+        self._members.pop(system.handle.value, None)
+
+    def step(self, k):
+        _check(lib.snp_batch_step(self._h, int(k)))
+
+    def sync(self):
+        _check(lib.snp_batch_sync(self._h))
+
+    def size(self):
+        n, t = ct.c_int32(), ct.c_int32()
+        _check(lib.snp_batch_size(self._h, ct.byref(n), ct.byref(t)))
+        return int(n.value), int(t.value)
+
+    def members(self):
+        n = self.size()[0]
+        arr = (ct.c_void_p * max(1, n))()
+        _check(lib.snp_batch_members(self._h, arr, n))
+        return [self._members[arr[i]] for i in range(n)]
+
+    def status(self):
+        """(members in current order, executed steps, done flags)."""
+        mem = self.members()
+        n = len(mem)
+        steps = np.zeros(max(1, n), np.int64)
+        done = np.zeros(max(1, n), np.int32)
+        if n:
+            _check(lib.snp_batch_status(self._h, steps.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                        done.ctypes.data_as(ct.POINTER(ct.c_int32))))
+        return mem, steps[:n], done[:n].astype(bool)
+
+    @property
+    def stream(self):
+        return self._torch_stream
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib.snp_batch_destroy(self._h))
+            self._h = ct.c_void_p()
+            self._members = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

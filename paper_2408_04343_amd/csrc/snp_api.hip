@@ -14,18 +14,20 @@
 #include <vector>
 
 #include "snp.h"
+#include "snp_host.h"
 #include "snp_internal.h"
 
 using namespace snp;
 
-namespace {
-
+namespace snp {
 thread_local std::string g_last_error;
-
 int fail(int status, const std::string& msg) {
   g_last_error = msg;
   return status;
 }
+}  // namespace snp
+
+namespace {
 
 #define HIPCHK(expr)                                                                  \
   do {                                                                                \
@@ -46,9 +48,8 @@ int32_t emit_width(int32_t pmax) {
   return w;
 }
 
-// LDS budget of one pull block: the whole CU for 4096-neuron tiles (one
-// block per CU), half of it for 2048-neuron tiles (two blocks per CU).
-int64_t pull_lds_budget(int32_t tb) { return tb >= 12 ? kPullLdsBytes : kPullLdsBytes / 2; }
+// LDS budget of one pull block: the whole compute unit (one block per CU).
+int64_t pull_lds_budget(int32_t) { return kPullLdsBytes; }
 
 // Sources per LDS chunk of emitted values: what is left of the block's LDS
 // after the accumulator and the staging words, below 2^(32 - tile bits) so
@@ -108,69 +109,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
 
 }  // namespace
 
-struct snp_sys {
-  snp_opts opts{};
-  int dev = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  SysDev d{};
-  int32_t q = 0, m = 0, z = 0, layout = 0;
-  int64_t nnz = 0;
-  std::vector<void*> allocs;
-  std::vector<int32_t> h_rid, h_slot, h_rs, h_out_ptr, h_out_col, h_in_ptr, h_in_src;
-  int32_t* scratch = nullptr;            // [4][q] materialized C, D, S, pend
-  unsigned long long* dig_tmp = nullptr;
-  int32_t* slot_of = nullptr;            // caller id -> slot
-  int32_t chunk = kDefaultChunk;
-  hipGraphExec_t graph = nullptr;
-  bool graph_tried = false;
-  int in_batch = 0;
-  int64_t device_bytes = 0;
-
-  void* dalloc(size_t bytes) {
-    if (bytes == 0) bytes = 4;
-    void* p = nullptr;
-    if (opts.alloc) {
-      p = opts.alloc(opts.alloc_ctx, bytes, (void*)stream);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-    }
-    if (p) {
-      allocs.push_back(p);
-      device_bytes += (int64_t)bytes;
-    }
-    return p;
-  }
-  void release() {
-    if (graph) {
-      (void)hipGraphExecDestroy(graph);
-      graph = nullptr;
-    }
-    if (stream) (void)hipStreamSynchronize(stream);
-    for (void* p : allocs) {
-      if (opts.free) opts.free(opts.alloc_ctx, p, (void*)stream);
-      else (void)hipFree(p);
-    }
-    allocs.clear();
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
-    stream = nullptr;
-  }
-};
-
 namespace {
-
-struct DevScope {
-  int prev = -1;
-  bool ok = true;
-  explicit DevScope(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) ok = false;
-    else if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DevScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 template <class T>
 int upload(snp_sys* s, T** dst, const T* src, size_t n) {
@@ -204,6 +143,7 @@ struct StateInfo {
 };
 
 int query(snp_sys* s, StateInfo* si) {
+  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   Ctl c;
   HIPCHK(hipMemcpy(&c, s->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -493,7 +433,13 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   d.seed = o.seed;
   d.ring = o.ring;
   d.emit_w = emit_width(pmax_all);
-  d.pull_tb = o.pull_tile_log2 == 11 ? 11 : 12;
+  if (o.emit_bits != 0) {
+    if (o.emit_bits != 1 && o.emit_bits != 2 && o.emit_bits != 4 && o.emit_bits != 8 && o.emit_bits != 16)
+      return bail(fail(SNP_EINVAL, "emit_bits must be 0, 1, 2, 4, 8 or 16"));
+    if (o.emit_bits < d.emit_w) return bail(fail(SNP_EINVAL, "emit_bits too small for the largest p"));
+    d.emit_w = o.emit_bits;
+  }
+  d.pull_tb = 12;
   d.pull_chunk = pull_chunk_sources(d.emit_w, d.pull_tb);
 
   int st;
@@ -507,7 +453,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     if ((st = upload(s, &p, rs.data(), rs.size())) != SNP_OK) return bail(st);
     d.rs = p;
     // packed 8-byte records when every rule fits them
-    bool fits8 = true;
+    bool fits8 = !(o.flags & SNP_F_WIDE_RULES);
     for (int32_t x = 0; x < m && fits8; ++x) {
       const RuleRec& R = rec[x];
       const bool dead = R.period == 0 && R.lo < 0;
@@ -537,6 +483,13 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     if ((st = upload(s, &s->slot_of, s->h_slot.data(), (size_t)m)) != SNP_OK) return bail(st);
   }
   if ((st = alloc_fill(s, (void**)&d.ctl, sizeof(Ctl), 0)) != SNP_OK) return bail(st);
+  {
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.k_limit = INT64_MAX;
+    if (hipMemcpyAsync(d.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return bail(fail(SNP_EDEVICE, "control block upload failed"));
+  }
   if ((st = alloc_fill(s, (void**)&s->scratch, 16 * (size_t)q, 0)) != SNP_OK) return bail(st);
   if ((st = alloc_fill(s, (void**)&s->dig_tmp, 32, 0)) != SNP_OK) return bail(st);
   if (d.flags & F_DIGEST)
@@ -811,6 +764,7 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
   std::memset(&c, 0, sizeof(c));
   c.k_base = k;
   c.k_exec = k;
+  c.k_limit = INT64_MAX;
   if (k >= 1) c.active[(k - 1) % 3] = 1;
   HIPCHK(hipMemcpyAsync(s->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
   if (s->d.flags & F_COUNTERS)
@@ -876,6 +830,16 @@ int snp_info(snp_sys* s, snp_info_t* o) {
 }
 
 void* snp_stream(snp_sys* s) { return s ? (void*)s->stream : nullptr; }
+
+int snp_set_step_limit(snp_sys* s, int64_t limit) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  DevScope ds(s->dev);
+  const int64_t v = limit < 0 ? INT64_MAX : limit;
+  hipStream_t st = s->batch_stream ? s->batch_stream : s->stream;
+  HIPCHK(hipMemcpyAsync(&s->d.ctl->k_limit, &v, sizeof(v), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SNP_OK;
+}
 
 int snp_destroy(snp_sys* s) {
   if (!s) return SNP_OK;

@@ -1,0 +1,334 @@
+// Batched form of the step: many independent systems advanced by one launch
+// per step.  The members' descriptors and a tile table (block -> member,
+// block within the member) live in device memory; launches are captured in
+// graphs sized by capacity, so adding or removing members only rewrites the
+// tables.  Each member keeps its own control block (step index, halting,
+// step limit), which makes its computation independent of the batch.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "snp.h"
+#include "snp_host.h"
+#include "snp_internal.h"
+
+using namespace snp;
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      return fail(e_ == hipErrorOutOfMemory ? SNP_ENOMEM : SNP_EDEVICE,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    }                                                                                 \
+  } while (0)
+
+struct snp_batch {
+  snp_batch_opts opts{};
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<snp_sys*> members;
+  SysDev proto{};
+  bool has_proto = false;
+  // device tables
+  SysDev* d_members = nullptr;
+  int2* d_tiles = nullptr;
+  int32_t* d_counts = nullptr;  // [0] members (advance, status), [1] tiles (step launches)
+  int64_t* d_steps = nullptr;
+  int32_t* d_done = nullptr;
+  int32_t cap_members = 0, cap_tiles = 0;
+  int32_t ntiles = 0;
+  size_t lds = 0;
+  // captured chunk
+  hipGraphExec_t graph = nullptr;
+  int32_t graph_cap_members = 0, graph_cap_tiles = 0;
+  size_t graph_lds = 0;
+  bool dirty = true;  // tables need uploading
+
+  void free_tables() {
+    (void)hipFree(d_members);
+    (void)hipFree(d_tiles);
+    (void)hipFree(d_counts);
+    (void)hipFree(d_steps);
+    (void)hipFree(d_done);
+    d_members = nullptr;
+    d_tiles = nullptr;
+    d_counts = nullptr;
+    d_steps = nullptr;
+    d_done = nullptr;
+  }
+};
+
+namespace {
+
+bool compatible(const SysDev& a, const SysDev& b) {
+  return a.layout == b.layout && a.rule_bytes == b.rule_bytes &&
+         (a.layout != L_CSR_PULL || (a.emit_w == b.emit_w && a.pull_tb == b.pull_tb)) &&
+         a.flags == b.flags;
+}
+
+int ensure_capacity(snp_batch* b, int32_t need_members, int32_t need_tiles) {
+  if (need_members <= b->cap_members && need_tiles <= b->cap_tiles && b->d_members) return SNP_OK;
+  int32_t cm = std::max(b->cap_members, 1), ct = std::max(b->cap_tiles, 1);
+  while (cm < need_members) cm *= 2;
+  while (ct < need_tiles) ct *= 2;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->free_tables();
+  HIPCHK(hipMalloc(&b->d_members, sizeof(SysDev) * (size_t)cm));
+  HIPCHK(hipMalloc(&b->d_tiles, sizeof(int2) * (size_t)ct));
+  HIPCHK(hipMalloc(&b->d_counts, 2 * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&b->d_steps, sizeof(int64_t) * (size_t)cm));
+  HIPCHK(hipMalloc(&b->d_done, sizeof(int32_t) * (size_t)cm));
+  b->cap_members = cm;
+  b->cap_tiles = ct;
+  b->dirty = true;
+  return SNP_OK;
+}
+
+// Rebuilds the member and tile tables and uploads them on the batch stream.
+int upload_tables(snp_batch* b) {
+  const int32_t n = (int32_t)b->members.size();
+  int32_t tiles = 0;
+  size_t lds = 0;
+  for (snp_sys* s : b->members) {
+    tiles += (s->q + step_tile(s->d) - 1) / step_tile(s->d);
+    if (s->d.layout == L_CSR_PULL) lds = std::max(lds, pull_lds_bytes(s->d));
+  }
+  int st = ensure_capacity(b, n, tiles);
+  if (st != SNP_OK) return st;
+  std::vector<SysDev> hm((size_t)std::max(n, 1));
+  std::vector<int2> ht((size_t)std::max(tiles, 1));
+  int32_t t = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    hm[i] = b->members[i]->d;
+    const int32_t nt = (b->members[i]->q + step_tile(hm[i]) - 1) / step_tile(hm[i]);
+    for (int32_t x = 0; x < nt; ++x) ht[(size_t)t++] = make_int2(i, x);
+  }
+  // the host copies stay alive until the stream has consumed them
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (n) HIPCHK(hipMemcpyAsync(b->d_members, hm.data(), sizeof(SysDev) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+  if (tiles) HIPCHK(hipMemcpyAsync(b->d_tiles, ht.data(), sizeof(int2) * (size_t)tiles, hipMemcpyHostToDevice, b->stream));
+  const int32_t counts[2] = {n, tiles};
+  HIPCHK(hipMemcpyAsync(b->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->ntiles = tiles;
+  b->lds = lds;
+  b->dirty = false;
+  return SNP_OK;
+}
+
+int launch_chunk_direct(snp_batch* b, int32_t n) {
+  for (int32_t j = 0; j < n; ++j)
+    HIPCHK(launch_step_batch(b->proto, b->d_members, b->d_tiles, b->d_counts + 1, b->ntiles, b->lds, j, b->stream));
+  HIPCHK(launch_advance_batch(b->d_members, b->d_counts, (int32_t)b->members.size(), n, b->stream));
+  return SNP_OK;
+}
+
+// Captures `chunk` launches over the full capacity (blocks past the current
+// tile count exit at once), so the graph survives membership changes.
+void capture(snp_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  bool ok = true;
+  for (int32_t j = 0; j < b->opts.chunk && ok; ++j)
+    ok = launch_step_batch(b->proto, b->d_members, b->d_tiles, b->d_counts + 1, b->cap_tiles, b->lds, j,
+                           b->stream) == hipSuccess;
+  if (ok) ok = launch_advance_batch(b->d_members, b->d_counts, b->cap_members, b->opts.chunk, b->stream) == hipSuccess;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (!ok || e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  b->graph = ex;
+  b->graph_cap_members = b->cap_members;
+  b->graph_cap_tiles = b->cap_tiles;
+  b->graph_lds = b->lds;
+}
+
+int add_member(snp_batch* b, snp_sys* s) {
+  if (!s) return fail(SNP_EINVAL, "null handle");
+  if (s->in_batch) return fail(SNP_EBUSY, "handle already in a batch");
+  if (s->dev != b->dev) return fail(SNP_EINVAL, "handle on another device");
+  if (!b->has_proto) {
+    b->proto = s->d;
+    b->has_proto = true;
+  } else if (!compatible(b->proto, s->d)) {
+    return fail(SNP_ENOTSUP, "member differs in layout, rule record size, emit width, tile or flags");
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->in_batch = 1;
+  s->batch_stream = b->stream;
+  b->members.push_back(s);
+  b->dirty = true;
+  return SNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void snp_batch_opts_default(snp_batch_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->chunk = 64;
+  o->capacity_members = 256;
+  o->capacity_tiles = 4096;
+}
+
+int snp_batch_create(int32_t n, snp_sys* const* systems, const snp_batch_opts* opts, snp_batch** out) {
+  if (!out || n < 0 || (n > 0 && !systems)) return fail(SNP_EINVAL, "bad argument");
+  *out = nullptr;
+  snp_batch* b = new (std::nothrow) snp_batch();
+  if (!b) return fail(SNP_ENOMEM, "host allocation failed");
+  if (opts) b->opts = *opts;
+  else snp_batch_opts_default(&b->opts);
+  if (b->opts.chunk <= 0) b->opts.chunk = 64;
+  if (b->opts.capacity_members <= 0) b->opts.capacity_members = 256;
+  if (b->opts.capacity_tiles <= 0) b->opts.capacity_tiles = 4096;
+  if (hipGetDevice(&b->dev) != hipSuccess) {
+    delete b;
+    return fail(SNP_EDEVICE, "no HIP device");
+  }
+  if (b->opts.stream) {
+    b->stream = (hipStream_t)b->opts.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(SNP_EDEVICE, "stream creation failed");
+    }
+    b->own_stream = true;
+  }
+  auto bail = [&](int st) {
+    for (snp_sys* s : b->members) {
+      s->in_batch = 0;
+      s->batch_stream = nullptr;
+    }
+    b->free_tables();
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return st;
+  };
+  int st = ensure_capacity(b, b->opts.capacity_members, b->opts.capacity_tiles);
+  if (st != SNP_OK) return bail(st);
+  for (int32_t i = 0; i < n; ++i)
+    if ((st = add_member(b, systems[i])) != SNP_OK) return bail(st);
+  if ((st = upload_tables(b)) != SNP_OK) return bail(st);
+  *out = b;
+  return SNP_OK;
+}
+
+int snp_batch_add(snp_batch* b, snp_sys* s) {
+  if (!b) return fail(SNP_EINVAL, "null batch");
+  DevScope ds(b->dev);
+  int st = add_member(b, s);
+  if (st != SNP_OK) return st;
+  return upload_tables(b);
+}
+
+int snp_batch_remove(snp_batch* b, snp_sys* s) {
+  if (!b || !s) return fail(SNP_EINVAL, "null argument");
+  auto it = std::find(b->members.begin(), b->members.end(), s);
+  if (it == b->members.end()) return fail(SNP_EINVAL, "handle is not a member");
+  DevScope ds(b->dev);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  *it = b->members.back();
+  b->members.pop_back();
+  s->in_batch = 0;
+  s->batch_stream = nullptr;
+  b->dirty = true;
+  return upload_tables(b);
+}
+
+int snp_batch_step(snp_batch* b, int64_t k) {
+  if (!b) return fail(SNP_EINVAL, "null batch");
+  if (k <= 0 || b->members.empty()) return SNP_OK;
+  DevScope ds(b->dev);
+  if (b->dirty) {
+    int st = upload_tables(b);
+    if (st != SNP_OK) return st;
+  }
+  const int32_t K = b->opts.chunk;
+  const bool want_graph = k >= K;
+  if (want_graph && (!b->graph || b->graph_cap_members != b->cap_members ||
+                     b->graph_cap_tiles != b->cap_tiles || b->graph_lds < b->lds))
+    capture(b);
+  while (k > 0) {
+    if (b->graph && k >= K) {
+      HIPCHK(hipGraphLaunch(b->graph, b->stream));
+      k -= K;
+      continue;
+    }
+    const int32_t n = (int32_t)std::min<int64_t>(k, K);
+    int st = launch_chunk_direct(b, n);
+    if (st != SNP_OK) return st;
+    k -= n;
+  }
+  return SNP_OK;
+}
+
+int snp_batch_sync(snp_batch* b) {
+  if (!b) return fail(SNP_EINVAL, "null batch");
+  DevScope ds(b->dev);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return SNP_OK;
+}
+
+int snp_batch_size(snp_batch* b, int32_t* members, int32_t* tiles) {
+  if (!b) return fail(SNP_EINVAL, "null batch");
+  if (members) *members = (int32_t)b->members.size();
+  if (tiles) *tiles = b->ntiles;
+  return SNP_OK;
+}
+
+int snp_batch_members(snp_batch* b, snp_sys** out, int32_t capacity) {
+  if (!b || (!out && capacity > 0)) return fail(SNP_EINVAL, "bad argument");
+  if (capacity < (int32_t)b->members.size()) return fail(SNP_EINVAL, "buffer too small");
+  for (size_t i = 0; i < b->members.size(); ++i) out[i] = b->members[i];
+  return SNP_OK;
+}
+
+int snp_batch_status(snp_batch* b, int64_t* steps, int32_t* done) {
+  if (!b) return fail(SNP_EINVAL, "null batch");
+  const int32_t n = (int32_t)b->members.size();
+  if (n == 0) return SNP_OK;
+  if (!steps || !done) return fail(SNP_EINVAL, "null output");
+  DevScope ds(b->dev);
+  HIPCHK(launch_batch_status(b->d_members, b->d_counts, b->cap_members, b->d_steps, b->d_done, b->stream));
+  HIPCHK(hipMemcpyAsync(steps, b->d_steps, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipMemcpyAsync(done, b->d_done, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return SNP_OK;
+}
+
+int snp_batch_destroy(snp_batch* b) {
+  if (!b) return SNP_OK;
+  DevScope ds(b->dev);
+  (void)hipStreamSynchronize(b->stream);
+  for (snp_sys* s : b->members) {
+    s->in_batch = 0;
+    s->batch_stream = nullptr;
+  }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->free_tables();
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return SNP_OK;
+}
+
+}  // extern "C"

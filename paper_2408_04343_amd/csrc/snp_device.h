@@ -1,0 +1,259 @@
+// Device-side building blocks of the SNP step kernels (not part of the ABI).
+#pragma once
+
+#include <algorithm>
+
+#include "snp_internal.h"
+
+namespace snp {
+
+// ---------------------------------------------------------------- helpers --
+
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+// Buffer b (0 or 1) of a double-buffered array member, chosen without
+// indexing the kernel argument (which would copy it to scratch memory).
+template <class T>
+__device__ __forceinline__ T pick(T a0, T a1, int64_t b) {
+  return (b & 1) ? a1 : a0;
+}
+
+// A decoded rule of the rule vector.
+struct Rule {
+  int32_t lo, period, c, p, d;
+};
+
+// Rule records: RB = 16, struct RuleRec; RB = 8, packed uint2 (see
+// snp_internal.h for the two encodings).
+template <int RB>
+__device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
+  Rule r;
+  if (RB == 16) {
+    const RuleRec x = s.rules[slot];
+    r.lo = x.lo;
+    r.period = x.period;
+    r.c = x.c;
+    r.p = (int32_t)(x.pd & 0xFFFFu);
+    r.d = (int32_t)(x.pd >> 16);
+  } else {
+    const uint2 x = s.rules8[slot];
+    const uint32_t per = x.x >> 24;
+    r.lo = per == R8_DEAD ? -1 : (int32_t)(x.x & 0xFFFFFFu);
+    r.period = per == R8_DEAD ? 0 : (int32_t)per;
+    r.c = (int32_t)(x.y & 0xFFFFu);
+    r.p = (int32_t)((x.y >> 16) & 0xFFu);
+    r.d = (int32_t)(x.y >> 24);
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
+  if (r.period == 0) return n == r.lo;
+  if (n < r.lo) return false;
+  if (r.period == 1) return true;
+  return ((uint32_t)(n - r.lo) % (uint32_t)r.period) == 0u;
+}
+
+// Rule chosen by open neuron i holding n spikes at step k, or -1.  `first`
+// is the already loaded record of slot r0 (valid if r0 < r1).
+template <int RB>
+__device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64_t k, int32_t n,
+                                               int32_t r0, int32_t r1, const Rule& first) {
+  if (r0 >= r1) return -1;
+  if (s.sel == SEL_FIRST) {
+    if (rule_applies(first, n)) return r0;
+    for (int32_t r = r0 + 1; r < r1; ++r)
+      if (rule_applies(load_rule<RB>(s, r), n)) return r;
+    return -1;
+  }
+  uint32_t cnt = rule_applies(first, n) ? 1u : 0u;
+  for (int32_t r = r0 + 1; r < r1; ++r) cnt += rule_applies(load_rule<RB>(s, r), n) ? 1u : 0u;
+  if (cnt == 0) return -1;
+  const uint64_t key = ((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)i;
+  const uint64_t h = mix64(mix64(s.seed) ^ key);
+  uint32_t j = (uint32_t)(((h >> 32) * (uint64_t)cnt) >> 32);
+  if (rule_applies(first, n)) {
+    if (j == 0) return r0;
+    --j;
+  }
+  for (int32_t r = r0 + 1; r < r1; ++r) {
+    if (rule_applies(load_rule<RB>(s, r), n)) {
+      if (j == 0) return r;
+      --j;
+    }
+  }
+  return -1;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    lo = __shfl_xor(lo, off, 64);
+    hi = __shfl_xor(hi, off, 64);
+    v += ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+// Adds v over the block and lets thread 0 add the total to *dst.
+template <int NT>
+__device__ __forceinline__ void block_add64(unsigned long long v, unsigned long long* dst,
+                                            unsigned long long* scratch) {
+  v = wave_sum64(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) scratch[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += scratch[w];
+    if (t) atomicAdd(dst, t);
+  }
+  __syncthreads();
+}
+
+// Per-thread contributions to the work counters of one step.
+struct Cnt {
+  unsigned long long v[NCOUNT];
+  __device__ void zero() {
+    for (int x = 0; x < NCOUNT; ++x) v[x] = 0;
+  }
+};
+enum { C_OPEN = 0, C_RULES, C_SEL, C_EMIT, C_EDGES, C_SENT, C_LOST, C_RECV, C_REOPEN, C_INEDGES };
+
+__device__ __forceinline__ uint64_t digest_term(int32_t i, int32_t C, int32_t D, int32_t S) {
+  const uint64_t key = (uint64_t)(uint32_t)i * 0x9E3779B97F4A7C15ull;
+  const uint64_t cd = ((uint64_t)(uint32_t)C << 32) | (uint64_t)(uint32_t)D;
+  return mix64(key ^ cd) + mix64(~key ^ (uint64_t)(uint32_t)S);
+}
+
+// Step prologue shared by all step kernels (tile = the block's index within
+// its system).  Returns false if the launch has nothing to do: the system
+// halted before step k, or reached its step limit.
+__device__ __forceinline__ bool step_prologue(const SysDev& s, int32_t tile, int32_t j, int64_t& k) {
+  Ctl* ctl = s.ctl;
+  k = ctl->k_base + j;
+  if (ctl->halted || k >= ctl->k_limit) return false;
+  if (k > 0 && ctl->active[(k - 1) % 3] == 0) {
+    // state k-1 was halted: step k-1 changed nothing; no later step runs
+    if (tile == 0 && threadIdx.x == 0) {
+      ctl->halt_step = k - 1;
+      ctl->halted = 1;
+    }
+    return false;
+  }
+  if (tile == 0 && threadIdx.x == 0) {
+    ctl->active[(k + 1) % 3] = 0;
+    ctl->k_exec = k + 1;
+    if (s.flags & F_DIGEST) s.digests[k % s.ring] = 0;
+    if (s.flags & F_COUNTERS)
+      for (int x = 0; x < NCOUNT; ++x) s.counters[((k + 1) % s.ring) * NCOUNT + x] = 0;
+  }
+  return true;
+}
+
+// What a neuron needs to take its step, loaded ahead of its use.
+struct NeuronIn {
+  int32_t C;        // C_k (after reception)
+  uint32_t meta;    // D_k and reception flag
+  int32_t r0, r1;   // rule slots
+  int32_t pend;     // pending slot (STANDARD, D_k == 1)
+  Rule rec;         // open neuron: record of slot r0 (if r0 < r1);
+                    // neuron opening now (STANDARD): record of the pending slot
+};
+
+template <int RB>
+__device__ __forceinline__ void prefetch_neuron(const SysDev& s, int32_t i, uint32_t meta,
+                                                NeuronIn& in) {
+  in.meta = meta;
+  in.r0 = s.rs[i];
+  in.r1 = s.rs[i + 1];
+  const int32_t D = (int32_t)(meta & META_D);
+  in.pend = -1;
+  int32_t slot = -1;
+  if (D == 0) {
+    if (in.r0 < in.r1) slot = in.r0;
+  } else if (D == 1 && s.sem == SEM_STANDARD) {
+    in.pend = s.pend[i];
+    slot = in.pend;
+  }
+  if (slot >= 0) in.rec = load_rule<RB>(s, slot);
+}
+
+// Selection + delay bookkeeping of neuron i.  Writes the neuron's state and
+// returns the spikes that leave it at this step and the rule slot that sends
+// them.
+struct Sel {
+  int32_t emit;   // spikes sent to every out-neighbour (0 = none)
+  int32_t erule;  // slot of the rule whose spikes leave
+  bool act;       // neuron is active in state k (closed, or has an applicable rule)
+};
+
+template <int RB, bool CNT>
+__device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k,
+                                             const NeuronIn& in, Cnt& cnt) {
+  const int32_t D = (int32_t)(in.meta & META_D);
+  int32_t Dn = 0, cons = 0, sel = -1;
+  Sel o{0, -1, false};
+  if (D == 0) {
+    sel = choose_rule<RB>(s, i, k, in.C, in.r0, in.r1, in.rec);
+    if (CNT) {
+      cnt.v[C_OPEN] += 1;
+      cnt.v[C_RULES] += (unsigned long long)(in.r1 - in.r0);
+    }
+    if (sel >= 0) {
+      int32_t rc, rp, rd;
+      if (sel == in.r0) {
+        rc = in.rec.c;
+        rp = in.rec.p;
+        rd = in.rec.d;
+      } else {
+        const Rule r = load_rule<RB>(s, sel);
+        rc = r.c;
+        rp = r.p;
+        rd = r.d;
+      }
+      cons = rc;
+      Dn = rd;
+      if (s.sem == SEM_PAPER || rd == 0) {
+        o.emit = rp;
+        o.erule = sel;
+      } else {
+        s.pend[i] = sel;
+      }
+      o.act = true;
+      if (CNT) cnt.v[C_SEL] += 1;
+    }
+  } else {
+    Dn = D - 1;
+    o.act = true;
+    if (CNT && Dn == 0) cnt.v[C_REOPEN] += 1;
+    if (s.sem == SEM_STANDARD && Dn == 0) {
+      o.erule = in.pend;
+      o.emit = in.rec.p;
+    }
+  }
+  const uint32_t rf = (s.sem == SEM_PAPER) ? (D == 0 ? 1u : 0u) : (Dn == 0 ? 1u : 0u);
+  s.C[i] = in.C - cons;
+  const uint32_t nm = (uint32_t)Dn | (rf << 31);
+  if (nm != in.meta) s.meta[i] = nm;
+  pick(s.S16[0], s.S16[1], k)[i] = sel >= 0 ? (uint16_t)(sel - in.r0) : S_NONE;
+  if (CNT && o.emit > 0) cnt.v[C_EMIT] += 1;
+  return o;
+}
+
+// Caller id of the rule recorded for neuron i in S16[buf], or -1.
+__device__ __forceinline__ int32_t spiking_id(const SysDev& s, int32_t buf, int32_t i) {
+  if (buf < 0) return -1;
+  const uint16_t x = pick(s.S16[0], s.S16[1], buf)[i];
+  return x == S_NONE ? -1 : s.rid[s.rs[i] + x];
+}
+
+}  // namespace snp

@@ -45,7 +45,8 @@ struct Ctl {
   int32_t halted;     // sticky: a kernel found the previous state halted
   int32_t overflow;   // sticky: a finalized count left the int32 range
   int32_t active[4];  // active[k % 3] != 0 iff state k had an active neuron
-  int32_t pad[6];
+  int64_t k_limit;    // steps with k >= k_limit are not executed
+  int32_t pad[4];
 };
 
 struct SysDev {
@@ -91,7 +92,26 @@ struct SysDev {
 
 // Host-side launchers (defined in snp_kernels.hip).
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_pull(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_push(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_pull_batch(const SysDev& s, const SysDev* members, const int2* tiles,
+                                  const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                                  hipStream_t st);
+hipError_t launch_step_push_batch(const SysDev& s, const SysDev* members, const int2* tiles,
+                                  const int32_t* ntiles, int32_t grid, int32_t j, hipStream_t st);
+int32_t push_tile();
 hipError_t launch_advance(Ctl* ctl, int32_t n, hipStream_t st);
+// Batched form: one launch steps every member; `proto` supplies the shared
+// kernel choice (layout, widths, flags), `members`/`tiles`/`ntiles` live in
+// device memory; `grid` blocks are launched and blocks past *ntiles exit.
+hipError_t launch_step_batch(const SysDev& proto, const SysDev* members, const int2* tiles,
+                             const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                             hipStream_t st);
+hipError_t launch_advance_batch(const SysDev* members, const int32_t* nmembers, int32_t cap,
+                                int32_t n, hipStream_t st);
+hipError_t launch_batch_status(const SysDev* members, const int32_t* nmembers, int32_t cap,
+                               int64_t* steps, int32_t* done, hipStream_t st);
+int32_t step_tile(const SysDev& s);  // neurons per block of the system's step kernel
 hipError_t launch_materialize(const SysDev& s, int32_t rbuf, int32_t sbuf, int32_t* outC,
                               int32_t* outD, int32_t* outS, int32_t* outP, hipStream_t st);
 hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, int32_t q,

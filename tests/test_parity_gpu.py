@@ -70,24 +70,6 @@ def test_hash_ragged_sizes_every_step(binding, layout, q):
         compare_every_step(binding, spec, layout, sem_name, sem, 25)
 
 
-@pytest.mark.parametrize("q", [2047, 2048, 2049, 6001])
-def test_pull_small_tile_every_step(binding, q):
-    # 2048-neuron tiles (two blocks per compute unit) on ragged sizes
-    spec = wl.small_random(q + 5, q, max_deg=9, max_rules=4, dmax=3, c0max=8,
-                           select=wl.SELECT_HASH, steps=25)
-    for sem_name, sem in SEMS:
-        compare_every_step(binding, spec, "csr_pull", sem_name, sem, 25, pull_tile_log2=11)
-
-
-def test_pull_small_tile_several_chunks(binding):
-    spec = wl.config2(q=700_000, steps=15)
-    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(15, want_state=False)
-    g = binding.System.from_spec(spec, layout="csr_pull", digest=True, pull_tile_log2=11)
-    assert g.info()["pull_chunks"] >= 2
-    g.step(15)
-    assert np.array_equal(g.read_digests(0, 15), ref["digests"])
-
-
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_hand_trace_h1(binding, layout):
     rules = np.array([(0, 1, 0, 1, 1, 2), (1, 1, 0, 1, 1, 0)], np.int32)
@@ -262,3 +244,79 @@ def test_digest_of_current_state(binding):
         o.step(n)
         g.step(n)
         assert g.digest() == o.digest()
+
+
+# ------------------------------------------------------------ batched form --
+
+def _batch_specs(n, seed=0, qmax=9000):
+    rng = np.random.default_rng(seed)
+    sizes = [1, 7, 4095, 4096, 4097] + [int(x) for x in rng.integers(50, qmax, size=n - 5)]
+    return [wl.small_random(1000 + seed * 100 + j, q, max_deg=min(10, max(q - 1, 0)), max_rules=4,
+                            dmax=3, c0max=8, select=wl.SELECT_HASH) for j, q in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_push", "optimized"])
+def test_batch_equals_alone(binding, layout):
+    specs = _batch_specs(14, seed=1)
+    steps = 150
+    refs = [oracle_of(sp, orc.SEM_STANDARD).step_record(steps, want_state=False) for sp in specs]
+    members = [binding.System.from_spec(sp, layout=layout, digest=True, emit_bits=2)
+               for sp in specs]
+    b = binding.Batch(members, chunk=32)
+    b.step(steps)      # 4 graph chunks + direct launches
+    b.sync()
+    for sp, g, ref in zip(specs, members, refs):
+        assert g.steps_done()[0] == ref["steps"], sp.name
+        assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"]), sp.name
+    mem, st, done = b.status()
+    for g, s_, d_ in zip(mem, st, done):
+        ref = refs[members.index(g)]
+        assert s_ == ref["steps"]
+    b.close()
+
+
+def test_batch_step_limits_and_membership(binding):
+    specs = _batch_specs(10, seed=2)
+    limits = [5, 40, 17, 100, 3, 64, 65, 1, 77, 30]
+    members = [binding.System.from_spec(sp, digest=True, emit_bits=2) for sp in specs]
+    for g, lim in zip(members, limits):
+        g.set_step_limit(lim)
+    b = binding.Batch(members[:6], chunk=16)
+    b.step(20)
+    b.remove(members[1])
+    b.add(members[7])
+    b.add(members[8])
+    b.step(50)
+    b.add(members[6])
+    b.add(members[9])
+    b.remove(members[0])
+    b.step(120)
+    mem, steps, done = b.status()
+    assert all(done)
+    for sp, g, lim in zip(specs, members, limits):
+        ref = oracle_of(sp, orc.SEM_STANDARD).step_record(lim, want_state=False)
+        n = g.steps_done()[0]
+        if g is members[1]:
+            assert n == 20          # left the batch after 20 steps
+        else:
+            assert n == ref["steps"], sp.name
+        assert np.array_equal(g.read_digests(0, n), ref["digests"][:n]), sp.name
+    # a member taken out keeps stepping alone from where it stopped
+    members[1].step(20)
+    ref = oracle_of(specs[1], orc.SEM_STANDARD).step_record(40, want_state=False)
+    assert np.array_equal(members[1].read_digests(0, 40), ref["digests"])
+    b.close()
+
+
+def test_batch_rejects_mixed_members(binding):
+    a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", emit_bits=2)
+    c = binding.System.from_spec(wl.small_random(2, 100), layout="csr_push")
+    b = binding.Batch([a])
+    with pytest.raises(binding.SnpError) as ei:
+        b.add(c)
+    assert ei.value.status == -6
+    with pytest.raises(binding.SnpError) as ei:
+        a.step(1)
+    assert ei.value.status == -5
+    b.close()
+    a.step(1)
