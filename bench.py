@@ -97,6 +97,67 @@ def count_bytes(binding, spec, layout, steps, warmup, info):
     return float(np.mean(b)), cnt
 
 
+def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0):
+    """Config 4: n independent systems (sizes log-uniform 1,000-262,144), one
+    batched launch per step vs the same systems stepped one after another.
+    Both time steps warmup..warmup+steps from the same initial states."""
+    from paper_2408_04343_amd import workloads as wl
+    t0 = time.time()
+    sizes = wl.config4_sizes(4, n)
+    if scale != 1.0:
+        sizes = np.maximum(1000, (sizes * scale).astype(np.int64))
+    specs = [wl.config4_system(j, int(sizes[j]), 4, steps) for j in range(n)]
+    gen_s = time.time() - t0
+    stream = torch.cuda.Stream()
+    t0 = time.time()
+    systems = [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2,
+                                        stream=stream.cuda_stream) for sp in specs]
+    create_s = time.time() - t0
+    total_q = int(sum(sp.q for sp in specs))
+    # plain: each system alone, one after another on one stream
+    for g in systems:
+        g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for g in systems:
+        g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_digest = [g.digest() for g in systems]
+    # batched: back to the initial states, one launch per step for all systems
+    for sp, g in zip(specs, systems):
+        g.write_state(sp.spikes0, np.zeros(sp.q, np.int32), None, None, 0)
+    b = binding.Batch(systems, chunk=chunk, capacity_members=n,
+                      capacity_tiles=sum((sp.q + 4095) // 4096 for sp in specs))
+    b.step(warmup)
+    b.sync()
+    bs = b.stream if b.stream is not None else stream
+    e0.record(bs)
+    b.step(steps)
+    e1.record(bs)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1)
+    members, done_steps, _ = b.status()
+    ntiles = b.size()[1]
+    b.close()
+    same = all(g.digest() == d for g, d in zip(systems, plain_digest))
+    for g in systems:
+        g.close()
+    nu = total_q * steps
+    log("batched %d systems (%d neurons, %d tiles): %.2f ms vs plain sequential %.2f ms" %
+        (n, total_q, ntiles, batch_ms, plain_ms))
+    return {"workload": "config4-batched: %d systems, sizes log-uniform 1,000-262,144 (total %d "
+                        "neurons), Poisson(12) out-degree, 1-4 rules, delays 0..3, hash choice, "
+                        "%d timed steps" % (n, total_q, steps),
+            "systems": n, "neurons": total_q, "steps": steps, "tiles": ntiles,
+            "batched": {"ms": batch_ms, "neuron_updates_per_s": nu / (batch_ms * 1e-3)},
+            "plain_sequential": {"ms": plain_ms, "neuron_updates_per_s": nu / (plain_ms * 1e-3)},
+            "speedup": plain_ms / batch_ms, "batched_equals_plain": bool(same),
+            "gen_s": round(gen_s, 1), "create_s": round(create_s, 1)}
+
+
 def cpu_baseline(spec, seconds):
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
@@ -122,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--q", type=int, default=1 << 20)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scale", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator is a single-GPU build "
@@ -163,6 +226,9 @@ def main():
                 "kernel": "step_pull_kernel" if args.layout == "csr_pull" else "step_push_kernel",
                 "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
                 "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}
+    batched = None
+    if not args.no_batch:
+        batched = run_batched(binding, torch, scale=args.batch_scale)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for ~%.0f s ..." % args.cpu_seconds)
@@ -179,6 +245,7 @@ def main():
                    "rule_bytes": head["info"].get("rule_bytes")},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched_vs_plain": batched,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
                                 "over": "graph chunks of %d steps" % args.chunk},
         "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()

@@ -320,3 +320,52 @@ def test_batch_rejects_mixed_members(binding):
     assert ei.value.status == -5
     b.close()
     a.step(1)
+
+
+# ------------------------------------------------------ full-size samples --
+
+def test_config2_full_size_digests(binding):
+    # the benchmark's workload and launch configuration (pull layout, graph
+    # chunks of 64); the oracle follows 200 steps, every digest compared
+    spec = wl.config2(steps=200)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    ref = o.step_record(200, want_state=False)
+    g = binding.System.from_spec(spec, layout="csr_pull", digest=True, chunk=64)
+    g.step(200)
+    assert g.steps_done()[0] == ref["steps"]
+    assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"])
+    r = o.read()
+    assert np.array_equal(g.read_config(), r["C"])
+    assert np.array_equal(g.read_delays(), r["D"])
+    assert np.array_equal(g.read_spiking(), r["S"])
+
+
+@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push"])
+def test_config2_full_size_push_layouts(binding, layout):
+    spec = wl.config2(steps=40)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(40, want_state=False)
+    g = binding.System.from_spec(spec, layout=layout, digest=True)
+    g.step(40)
+    assert np.array_equal(g.read_digests(0, 40), ref["digests"])
+
+
+def test_config4_full_batch_sampled(binding):
+    # all 256 systems of the batched workload in one batch, 500 steps; the
+    # oracle recomputes a sample of members (the smallest, a middle one, the
+    # largest) and their digests must match at every step
+    sizes = wl.config4_sizes()
+    specs = [wl.config4_system(j, int(sizes[j]), steps=500) for j in range(256)]
+    import torch
+    stream = torch.cuda.Stream()
+    members = [binding.System.from_spec(sp, layout="csr_pull", emit_bits=2, digest=True,
+                                        ring=512, stream=stream.cuda_stream) for sp in specs]
+    b = binding.Batch(members, chunk=64, capacity_members=256,
+                      capacity_tiles=sum((sp.q + 4095) // 4096 for sp in specs))
+    b.step(500)
+    b.sync()
+    order = np.argsort(sizes)
+    for j in (int(order[0]), int(order[1]), int(order[128]), int(order[-1])):
+        ref = oracle_of(specs[j], orc.SEM_STANDARD).step_record(500, want_state=False)
+        assert members[j].steps_done()[0] == ref["steps"]
+        assert np.array_equal(members[j].read_digests(0, ref["steps"]), ref["digests"]), j
+    b.close()
