@@ -158,6 +158,55 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
             "gen_s": round(gen_s, 1), "create_s": round(create_s, 1)}
 
 
+def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64):
+    """Config 5: Poisson arrivals of requests with q ~ logU[1,000, 1,048,576]
+    and steps ~ logU[100, 10,000], hash choice.  Each request clones the
+    template nearest to its size (log scale), so a pool of templates stands in
+    for 120k distinct systems.  Runs at `rate` req/s and, if capacity_nu is
+    given, again at 0.7x the capacity it implies."""
+    from paper_2408_04343_amd import serve
+    from paper_2408_04343_amd import workloads as wl
+    t0 = time.time()
+    tq = np.unique(np.round(np.exp(np.linspace(np.log(1000), np.log(1 << 20), n_templates))).astype(int))
+    stream = torch.cuda.Stream()
+    templates = [binding.System.from_spec(wl.config5_system(1000 + j, int(q), 0, 0), emit_bits=2,
+                                          stream=stream.cuda_stream) for j, q in enumerate(tq)]
+    prep_s = time.time() - t0
+    logq = np.log(tq)
+
+    def make(rate_, dur, seed):
+        arr, q, steps, seeds = wl.config5_requests(seed=seed, rate=rate_, duration=dur)
+        idx = np.abs(np.log(q)[:, None] - logq[None, :]).argmin(axis=1)
+        return [serve.Request(rid=i, template=templates[idx[i]], steps=int(steps[i]),
+                              seed=int(seeds[i]), arrival=float(arr[i])) for i in range(len(arr))]
+
+    def one(rate_, dur, seed):
+        reqs = make(rate_, dur, seed)
+        mean_work = float(np.mean([r.q * r.steps for r in reqs])) if reqs else 0.0
+        srv = serve.Server(tick_steps=tick, chunk=tick, max_members=256, max_tiles=8192)
+        st = srv.run(reqs, duration=dur)
+        srv.close()
+        st.update({"rate_req_per_s": rate_, "duration_s": dur,
+                   "offered_neuron_updates_per_s": rate_ * mean_work})
+        log("served at %.0f req/s for %.0f s: %d/%d completed, %.3e nu/s, p50 %s s, p99 %s s" %
+            (rate_, dur, st["completed"], st["arrived"], st["completed_neuron_updates_per_s"],
+             st["latency_p50_s"], st["latency_p99_s"]))
+        return st, mean_work
+
+    over, mean_work = one(rate, seconds, 5)
+    out = {"workload": "config5-served: Poisson arrivals, q ~ logU[1,000, 1,048,576] (nearest of %d "
+                       "templates), steps ~ logU[100, 10,000], Poisson(16) out-degree, hash choice"
+                       % len(tq),
+           "templates": len(tq), "template_prep_s": round(prep_s, 1), "tick_steps": tick,
+           "at_rate": over}
+    if capacity_nu:
+        sub_rate = 0.7 * capacity_nu / mean_work
+        out["at_0.7x_capacity"], _ = one(sub_rate, seconds, 6)
+    for t in templates:
+        t.close()
+    return out
+
+
 def cpu_baseline(spec, seconds):
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
@@ -185,6 +234,9 @@ def main():
     ap.add_argument("--q", type=int, default=1 << 20)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator is a single-GPU build "
@@ -229,6 +281,10 @@ def main():
     batched = None
     if not args.no_batch:
         batched = run_batched(binding, torch, scale=args.batch_scale)
+    served = None
+    if not args.no_serve:
+        cap = batched["batched"]["neuron_updates_per_s"] if batched else value
+        served = run_served(binding, torch, args.serve_rate, args.serve_seconds, capacity_nu=cap)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for ~%.0f s ..." % args.cpu_seconds)
@@ -246,6 +302,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_vs_plain": batched,
+        "served": served,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
                                 "over": "graph chunks of %d steps" % args.chunk},
         "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()

@@ -247,6 +247,14 @@ int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layo
 int snp_paper_sizes(int64_t q, int64_t m, int64_t z, int64_t* sparse, int64_t* ell,
                     int64_t* compressed);
 
+/* A new system with the same neurons, rules and synapses as `base` (whose
+ * device representation it shares, read-only) and its own state: initial
+ * spikes `spikes0` (host [q]; NULL = those of the original), HASH key
+ * `seed`, step 0.  `stream` = hipStream_t for its own calls (NULL = the
+ * original's).  The original cannot be destroyed while clones exist
+ * (SNP_EBUSY).  Cloning a clone shares the original's structure.          */
+int snp_clone(snp_sys* base, const int32_t* spikes0, uint64_t seed, void* stream, snp_sys** out);
+
 /* Frees the handle and its device memory (waits for its stream). */
 int snp_destroy(snp_sys* sys);
 
@@ -281,7 +289,8 @@ void snp_batch_opts_default(snp_batch_opts* opts);
 /* Creates a batch of the n handles (n may be 0). */
 int snp_batch_create(int32_t n, snp_sys* const* systems, const snp_batch_opts* opts,
                      snp_batch** out);
-/* Adds / removes one member (waits for the streams involved). */
+/* Adds / removes one member (waits for the streams involved; the device
+ * tables are rewritten once before the next launch).                       */
 int snp_batch_add(snp_batch* b, snp_sys* sys);
 int snp_batch_remove(snp_batch* b, snp_sys* sys);
 /* Enqueues k steps of every member on the batch stream; returns at once. */

@@ -34,7 +34,7 @@ SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_
            "snp_strerror", "snp_last_error", "snp_set_step_limit", "snp_batch_opts_default",
            "snp_batch_create", "snp_batch_add", "snp_batch_remove", "snp_batch_step",
            "snp_batch_sync", "snp_batch_size", "snp_batch_members", "snp_batch_status",
-           "snp_batch_destroy"]
+           "snp_batch_destroy", "snp_clone"]
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
@@ -121,6 +121,7 @@ def _load():
         "snp_batch_members": (ct.c_int, [vp, P(vp), ct.c_int32]),
         "snp_batch_status": (ct.c_int, [vp, i64p, i32p]),
         "snp_batch_destroy": (ct.c_int, [vp]),
+        "snp_clone": (ct.c_int, [vp, i32p, ct.c_uint64, vp, P(vp)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -337,6 +338,23 @@ class System:
         i = Info()
         _check(lib.snp_info(self._h, ct.byref(i)))
         return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "pad"}
+
+    def clone(self, seed=None, spikes0=None, stream=None):
+        """A new system sharing this one's rules and synapses on the device."""
+        c = System.__new__(System)
+        c._h = ct.c_void_p()
+        c.q, c.m, c.layout_id = self.q, self.m, self.layout_id
+        c._torch_stream, c._mem = None, self._mem
+        c._base = self           # keeps the original alive while the clone lives
+        s0 = _i32(spikes0) if spikes0 is not None else None
+        if s0 is not None and s0.shape != (self.q,):
+            raise ValueError("spikes0 must have q entries")
+        st = int(stream) if stream is not None else (
+            self._torch_stream.cuda_stream if self._torch_stream is not None else None)
+        _check(lib.snp_clone(self._h, _ptr(s0) if s0 is not None else None,
+                             (int(seed) if seed is not None else 0) & 0xFFFFFFFFFFFFFFFF,
+                             st, ct.byref(c._h)))
+        return c
 
     def set_step_limit(self, limit):
         _check(lib.snp_set_step_limit(self._h, -1 if limit is None else int(limit)))

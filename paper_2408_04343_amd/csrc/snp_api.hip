@@ -115,7 +115,11 @@ template <class T>
 int upload(snp_sys* s, T** dst, const T* src, size_t n) {
   *dst = (T*)s->dalloc(sizeof(T) * std::max<size_t>(n, 1));
   if (!*dst) return fail(SNP_ENOMEM, "device allocation failed");
-  if (n) HIPCHK(hipMemcpyAsync(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice, s->stream));
+  if (n) {
+    // the host array may be a temporary: wait until the copy has read it
+    HIPCHK(hipMemcpyAsync(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
   return SNP_OK;
 }
 
@@ -216,6 +220,47 @@ int capture_graph(snp_sys* s) {
   return SNP_OK;
 }
 
+// State arrays of a system (everything a step writes): C_0, D_0 = 0, no
+// pending rule, no spiking record, cleared receive buffers, a fresh control
+// block and the digest / counter rings.  Shared by snp_create and snp_clone.
+int alloc_state(snp_sys* s, const int32_t* spikes0) {
+  SysDev& d = s->d;
+  const int32_t q = s->q;
+  int st;
+  if ((st = upload(s, &d.C, spikes0, (size_t)q)) != SNP_OK) return st;
+  if ((st = alloc_fill(s, (void**)&d.meta, 4 * (size_t)q, 0)) != SNP_OK) return st;
+  if ((st = alloc_fill(s, (void**)&d.pend, 4 * (size_t)q, 0xFF)) != SNP_OK) return st;
+  for (int b = 0; b < 2; ++b)
+    if ((st = alloc_fill(s, (void**)&d.S16[b], 2 * (size_t)q, 0xFF)) != SNP_OK) return st;
+  if ((st = alloc_fill(s, (void**)&d.ctl, sizeof(Ctl), 0)) != SNP_OK) return st;
+  Ctl c0;
+  std::memset(&c0, 0, sizeof(c0));
+  c0.k_limit = INT64_MAX;
+  s->ctl_init = c0;  // the host copy must outlive the asynchronous upload
+  HIPCHK(hipMemcpyAsync(d.ctl, &s->ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  if ((st = alloc_fill(s, (void**)&s->scratch, 16 * (size_t)q, 0)) != SNP_OK) return st;
+  if ((st = alloc_fill(s, (void**)&s->dig_tmp, 32, 0)) != SNP_OK) return st;
+  d.digests = nullptr;
+  d.counters = nullptr;
+  if (d.flags & F_DIGEST)
+    if ((st = alloc_fill(s, (void**)&d.digests, 8 * (size_t)d.ring, 0)) != SNP_OK) return st;
+  if (d.flags & F_COUNTERS)
+    if ((st = alloc_fill(s, (void**)&d.counters, 8 * NCOUNT * (size_t)(d.ring + 1), 0)) != SNP_OK) return st;
+  d.emit[0] = d.emit[1] = nullptr;
+  d.delta[0] = d.delta[1] = nullptr;
+  if (d.layout == L_CSR_PULL) {
+    const size_t tile = (size_t)1 << d.pull_tb;
+    const size_t tiles = ((size_t)q + tile - 1) / tile;
+    const size_t words = tiles * tile * d.emit_w / 32;
+    for (int b = 0; b < 2; ++b)
+      if ((st = alloc_fill(s, (void**)&d.emit[b], 4 * words, 0)) != SNP_OK) return st;
+  } else {
+    for (int b = 0; b < 2; ++b)
+      if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return st;
+  }
+  return SNP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -312,6 +357,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   s->nnz = nsyn;
   s->layout = o.layout;
   s->chunk = o.chunk;
+  s->h_spikes0.assign(spikes0, spikes0 + q);
 
   auto bail = [&](int st) {
     s->release();
@@ -443,11 +489,6 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   d.pull_chunk = pull_chunk_sources(d.emit_w, d.pull_tb);
 
   int st;
-  if ((st = upload(s, &d.C, spikes0, (size_t)q)) != SNP_OK) return bail(st);
-  if ((st = alloc_fill(s, (void**)&d.meta, 4 * (size_t)q, 0)) != SNP_OK) return bail(st);
-  if ((st = alloc_fill(s, (void**)&d.pend, 4 * (size_t)q, 0xFF)) != SNP_OK) return bail(st);
-  for (int b = 0; b < 2; ++b)
-    if ((st = alloc_fill(s, (void**)&d.S16[b], 2 * (size_t)q, 0xFF)) != SNP_OK) return bail(st);
   {
     int32_t* p;
     if ((st = upload(s, &p, rs.data(), rs.size())) != SNP_OK) return bail(st);
@@ -482,22 +523,6 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.rid = p;
     if ((st = upload(s, &s->slot_of, s->h_slot.data(), (size_t)m)) != SNP_OK) return bail(st);
   }
-  if ((st = alloc_fill(s, (void**)&d.ctl, sizeof(Ctl), 0)) != SNP_OK) return bail(st);
-  {
-    Ctl c0;
-    std::memset(&c0, 0, sizeof(c0));
-    c0.k_limit = INT64_MAX;
-    if (hipMemcpyAsync(d.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, s->stream) != hipSuccess)
-      return bail(fail(SNP_EDEVICE, "control block upload failed"));
-  }
-  if ((st = alloc_fill(s, (void**)&s->scratch, 16 * (size_t)q, 0)) != SNP_OK) return bail(st);
-  if ((st = alloc_fill(s, (void**)&s->dig_tmp, 32, 0)) != SNP_OK) return bail(st);
-  if (d.flags & F_DIGEST)
-    if ((st = alloc_fill(s, (void**)&d.digests, 8 * (size_t)o.ring, 0)) != SNP_OK) return bail(st);
-  if (d.flags & F_COUNTERS)
-    if ((st = alloc_fill(s, (void**)&d.counters, 8 * NCOUNT * (size_t)(o.ring + 1), 0)) != SNP_OK)
-      return bail(st);
-
   if (pull) {
     int32_t* p;
     if ((st = upload(s, &p, s->h_in_ptr.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
@@ -544,11 +569,6 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
         lds_ready.fetch_or(bit);
       }
     }
-    const size_t tile = (size_t)1 << d.pull_tb;
-    const size_t tiles = ((size_t)q + tile - 1) / tile;
-    const size_t words = tiles * tile * d.emit_w / 32;
-    for (int b = 0; b < 2; ++b)
-      if ((st = alloc_fill(s, (void**)&d.emit[b], 4 * words, 0)) != SNP_OK) return bail(st);
     if (d.flags & F_COUNTERS) {
       std::vector<int32_t> deg((size_t)q);
       for (int32_t i = 0; i < q; ++i) deg[i] = op[(size_t)i + 1] - op[i];
@@ -556,8 +576,6 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       d.out_deg = p;
     }
   } else {
-    for (int b = 0; b < 2; ++b)
-      if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return bail(st);
     int32_t* p;
     if (d.flags & F_COUNTERS) {
       std::vector<int32_t> indeg((size_t)q, 0);
@@ -581,8 +599,47 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       if (hipSuccess != launch_build_ell(d, ell, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
     }
   }
+  if ((st = alloc_state(s, spikes0)) != SNP_OK) return bail(st);
   if (hipStreamSynchronize(s->stream) != hipSuccess)
     return bail(fail(SNP_EDEVICE, std::string("create: ") + hipGetErrorString(hipGetLastError())));
+  *out = s;
+  return SNP_OK;
+}
+
+int snp_clone(snp_sys* base, const int32_t* spikes0, uint64_t seed, void* stream, snp_sys** out) {
+  if (!out || !base) return fail(SNP_EINVAL, "null argument");
+  *out = nullptr;
+  snp_sys* root = base->base ? base->base : base;  // share the structure of the original
+  const int32_t q = root->q;
+  if (spikes0)
+    for (int32_t i = 0; i < q; ++i)
+      if (spikes0[i] < 0) return fail(SNP_EINVAL, "negative initial spikes");
+  snp_sys* s = new (std::nothrow) snp_sys();
+  if (!s) return fail(SNP_ENOMEM, "host allocation failed");
+  s->opts = root->opts;
+  s->opts.seed = seed;
+  s->dev = root->dev;
+  s->q = q;
+  s->m = root->m;
+  s->z = root->z;
+  s->nnz = root->nnz;
+  s->layout = root->layout;
+  s->chunk = root->chunk;
+  s->base = root;
+  s->d = root->d;  // structure pointers are shared; state pointers are replaced
+  s->d.seed = seed;
+  s->slot_of = root->slot_of;
+  DevScope ds(s->dev);
+  s->stream = stream ? (hipStream_t)stream : root->stream;
+  int st = alloc_state(s, spikes0 ? spikes0 : root->h_spikes0.data());
+  if (st == SNP_OK && hipStreamSynchronize(s->stream) != hipSuccess)
+    st = fail(SNP_EDEVICE, std::string("clone: ") + hipGetErrorString(hipGetLastError()));
+  if (st != SNP_OK) {
+    s->release();
+    delete s;
+    return st;
+  }
+  root->clones++;
   *out = s;
   return SNP_OK;
 }
@@ -725,18 +782,19 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
   if (!s || !C || !D || k < 0 || k > 0x7FFFFFFFLL) return fail(SNP_EINVAL, "bad argument");
   if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
   const int32_t q = s->q;
+  const snp_sys* root = s->base ? s->base : s;
   for (int32_t i = 0; i < q; ++i) {
     if (C[i] < 0 || D[i] < 0) return fail(SNP_EINVAL, "negative count or delay");
     const bool owns_p = P && P[i] >= 0;
     if (P && P[i] >= s->m) return fail(SNP_EINVAL, "pending rule out of range");
     if (owns_p) {
-      const int32_t sl = s->h_slot[P[i]];
-      if (sl < s->h_rs[i] || sl >= s->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "pending rule of another neuron");
+      const int32_t sl = root->h_slot[P[i]];
+      if (sl < root->h_rs[i] || sl >= root->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "pending rule of another neuron");
     }
     if (S && S[i] >= 0) {
       if (S[i] >= s->m) return fail(SNP_EINVAL, "spiking rule out of range");
-      const int32_t sl = s->h_slot[S[i]];
-      if (sl < s->h_rs[i] || sl >= s->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "spiking rule of another neuron");
+      const int32_t sl = root->h_slot[S[i]];
+      if (sl < root->h_rs[i] || sl >= root->h_rs[(size_t)i + 1]) return fail(SNP_EINVAL, "spiking rule of another neuron");
     }
     if (s->opts.semantics == SNP_SEM_STANDARD && D[i] > 0 && !owns_p)
       return fail(SNP_EINVAL, "closed neuron without pending rule");
@@ -796,7 +854,7 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
     HIPCHK(hipMemcpy(tmp.data(), s->d.ell, 4 * (size_t)need, hipMemcpyDeviceToHost));
     for (int64_t row = 0; row <= z; ++row)
       for (int32_t sl = 0; sl < m; ++sl) {
-        const int64_t src = (row * m + sl) * 2, dst = (row * m + s->h_rid[sl]) * 2;
+        const int64_t src = (row * m + sl) * 2, dst = (row * m + (s->base ? s->base : s)->h_rid[sl]) * 2;
         out[dst] = tmp[(size_t)src];
         out[dst + 1] = tmp[(size_t)src + 1];
       }
@@ -844,6 +902,8 @@ int snp_set_step_limit(snp_sys* s, int64_t limit) {
 int snp_destroy(snp_sys* s) {
   if (!s) return SNP_OK;
   if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
+  if (s->clones > 0) return fail(SNP_EBUSY, "clones of this handle still exist");
+  if (s->base) s->base->clones--;
   {
     DevScope ds(s->dev);
     s->release();

@@ -236,9 +236,7 @@ int snp_batch_create(int32_t n, snp_sys* const* systems, const snp_batch_opts* o
 int snp_batch_add(snp_batch* b, snp_sys* s) {
   if (!b) return fail(SNP_EINVAL, "null batch");
   DevScope ds(b->dev);
-  int st = add_member(b, s);
-  if (st != SNP_OK) return st;
-  return upload_tables(b);
+  return add_member(b, s);  // tables are uploaded before the next launch
 }
 
 int snp_batch_remove(snp_batch* b, snp_sys* s) {
@@ -251,8 +249,8 @@ int snp_batch_remove(snp_batch* b, snp_sys* s) {
   b->members.pop_back();
   s->in_batch = 0;
   s->batch_stream = nullptr;
-  b->dirty = true;
-  return upload_tables(b);
+  b->dirty = true;  // tables are uploaded before the next launch
+  return SNP_OK;
 }
 
 int snp_batch_step(snp_batch* b, int64_t k) {
@@ -291,6 +289,11 @@ int snp_batch_sync(snp_batch* b) {
 
 int snp_batch_size(snp_batch* b, int32_t* members, int32_t* tiles) {
   if (!b) return fail(SNP_EINVAL, "null batch");
+  if (b->dirty) {
+    DevScope ds(b->dev);
+    int st = upload_tables(b);
+    if (st != SNP_OK) return st;
+  }
   if (members) *members = (int32_t)b->members.size();
   if (tiles) *tiles = b->ntiles;
   return SNP_OK;
@@ -309,6 +312,10 @@ int snp_batch_status(snp_batch* b, int64_t* steps, int32_t* done) {
   if (n == 0) return SNP_OK;
   if (!steps || !done) return fail(SNP_EINVAL, "null output");
   DevScope ds(b->dev);
+  if (b->dirty) {
+    int st = upload_tables(b);
+    if (st != SNP_OK) return st;
+  }
   HIPCHK(launch_batch_status(b->d_members, b->d_counts, b->cap_members, b->d_steps, b->d_done, b->stream));
   HIPCHK(hipMemcpyAsync(steps, b->d_steps, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, b->stream));
   HIPCHK(hipMemcpyAsync(done, b->d_done, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, b->stream));

@@ -50,6 +50,10 @@ struct snp_sys {
   int in_batch = 0;
   hipStream_t batch_stream = nullptr;   // stream of the batch the handle is in
   int64_t device_bytes = 0;
+  snp_sys* base = nullptr;              // clones: the handle whose structure they share
+  int clones = 0;                       // live clones sharing this handle's structure
+  std::vector<int32_t> h_spikes0;       // C_0, for clones without their own
+  snp::Ctl ctl_init{};                  // host copy of the initial control block
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 4;

@@ -369,3 +369,66 @@ def test_config4_full_batch_sampled(binding):
         assert members[j].steps_done()[0] == ref["steps"]
         assert np.array_equal(members[j].read_digests(0, ref["steps"]), ref["digests"]), j
     b.close()
+
+
+def test_clone_shares_structure_and_matches_oracle(binding):
+    spec = wl.small_random(555, 7000, max_deg=10, max_rules=4, dmax=3, select=wl.SELECT_HASH)
+    base = binding.System.from_spec(spec, digest=True)
+    rng = np.random.default_rng(9)
+    clones = []
+    for x in range(3):
+        s0 = rng.integers(0, 9, size=spec.q).astype(np.int32)
+        seed = 1000 + x
+        c = base.clone(seed=seed, spikes0=s0)
+        assert c.info()["device_bytes"] < base.info()["device_bytes"]
+        clones.append((c, s0, seed))
+    base.step(30)
+    for c, s0, seed in clones:
+        c.step(30 + seed % 7)
+    assert binding.lib.snp_destroy(base.handle) == -5   # clones still alive
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(30, want_state=False)
+    assert np.array_equal(base.read_digests(0, 30), ref["digests"])
+    for c, s0, seed in clones:
+        n = 30 + seed % 7
+        o = orc.OracleSystem(spec.q, s0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
+                             orc.SEL_HASH, seed)
+        r = o.step_record(n, want_state=False)
+        assert np.array_equal(c.read_digests(0, n), r["digests"])
+        c.close()
+    base.close()
+
+
+# -------------------------------------------------------------- served form --
+
+def test_served_results_equal_alone(binding):
+    from paper_2408_04343_amd import serve
+    rng = np.random.default_rng(17)
+    specs = [wl.small_random(800 + j, q, max_deg=10, max_rules=4, dmax=3, c0max=8,
+                             select=wl.SELECT_HASH) for j, q in enumerate([300, 2000, 5000, 9000])]
+    templates = [binding.System.from_spec(sp, emit_bits=2) for sp in specs]
+    reqs = []
+    for r in range(48):
+        t = int(rng.integers(0, len(specs)))
+        s0 = rng.integers(0, 9, size=specs[t].q).astype(np.int32) if r % 3 == 0 else None
+        reqs.append(serve.Request(rid=r, template=templates[t], steps=int(rng.integers(5, 300)),
+                                  seed=int(rng.integers(0, 2 ** 62)),
+                                  arrival=float(r) * 0.0002, spikes0=s0))
+    results = {}
+
+    def on_done(req, sysg):
+        results[req.rid] = (sysg.steps_done()[0], sysg.digest())
+
+    srv = serve.Server(tick_steps=16, chunk=16, max_members=6, on_done=on_done)
+    stats = srv.run(reqs, drain=True)
+    srv.close()
+    assert stats["completed"] == len(reqs)
+    assert stats["admission_deferrals"] > 0      # requests waited for a slot
+    assert max(r.admitted for r in reqs) > min(r.finished for r in reqs)   # joined mid-run
+    for req in reqs:
+        t = templates.index(req.template)
+        sp = specs[t]
+        s0 = req.spikes0 if req.spikes0 is not None else sp.spikes0
+        o = orc.OracleSystem(sp.q, s0, sp.rules, sp.src, sp.dst, orc.SEM_STANDARD, orc.SEL_HASH,
+                             req.seed)
+        n = o.step(req.steps)
+        assert results[req.rid] == (n, o.digest()), req.rid
