@@ -220,6 +220,47 @@ def cpu_baseline(spec, seconds):
             "sample": "%s: first %d steps, single-threaded C oracle (%.1f s)" % (spec.name, n, dt)}
 
 
+KERNEL_SOURCES = ["paper_2408_04343_amd/csrc/snp_step_pull.hip", "paper_2408_04343_amd/csrc/snp_device.h",
+                  "paper_2408_04343_amd/csrc/snp_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the pull step kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_step_pull_kernel_config2.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    if t.get("source_hash") != kernel_source_hash():
+        return None, t
+    return t.get("traffic_bytes_per_launch"), t
+
+
+def copy_probe(mib):
+    """A plain device copy of known size (calibrates the memory counters)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,7 +278,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0)
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator is a single-GPU build "
               "(no collectives); run with --gpus 1", file=sys.stderr)
@@ -272,9 +317,11 @@ def main():
     head = results[args.layout]
     value = spec.q * args.steps / (head["total_ms"] * 1e-3)
     roof = None
+    traffic, _tinfo = measured_traffic() if args.layout == "csr_pull" else (None, None)
     if "alg_GBps" in head:
         roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(head["frac_of_peak"], 4), "traffic": None,
+                "unit": "GB/s", "frac": round(head["frac_of_peak"], 4),
+                "traffic": None if traffic is None else int(traffic),
                 "kernel": "step_pull_kernel" if args.layout == "csr_pull" else "step_push_kernel",
                 "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
                 "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}

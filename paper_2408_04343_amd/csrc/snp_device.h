@@ -31,29 +31,49 @@ struct Rule {
   int32_t lo, period, c, p, d;
 };
 
-// Rule records: RB = 16, struct RuleRec; RB = 8, packed uint2 (see
+// Rule records as stored: RB = 16, struct RuleRec; RB = 8, packed uint2 (see
 // snp_internal.h for the two encodings).
 template <int RB>
-__device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
-  Rule r;
-  if (RB == 16) {
-    const RuleRec x = s.rules[slot];
-    r.lo = x.lo;
-    r.period = x.period;
-    r.c = x.c;
-    r.p = (int32_t)(x.pd & 0xFFFFu);
-    r.d = (int32_t)(x.pd >> 16);
-  } else {
-    const uint2 x = s.rules8[slot];
-    const uint32_t per = x.x >> 24;
-    r.lo = per == R8_DEAD ? -1 : (int32_t)(x.x & 0xFFFFFFu);
-    r.period = per == R8_DEAD ? 0 : (int32_t)per;
-    r.c = (int32_t)(x.y & 0xFFFFu);
-    r.p = (int32_t)((x.y >> 16) & 0xFFu);
-    r.d = (int32_t)(x.y >> 24);
-  }
-  return r;
+struct RawRule;
+template <>
+struct RawRule<8> {
+  uint2 w;
+};
+template <>
+struct RawRule<16> {
+  RuleRec w;
+};
+
+template <int RB>
+__device__ __forceinline__ RawRule<RB> load_raw(const SysDev& s, int32_t slot);
+template <>
+__device__ __forceinline__ RawRule<8> load_raw<8>(const SysDev& s, int32_t slot) {
+  return RawRule<8>{s.rules8[slot]};
 }
+template <>
+__device__ __forceinline__ RawRule<16> load_raw<16>(const SysDev& s, int32_t slot) {
+  return RawRule<16>{s.rules[slot]};
+}
+
+__device__ __forceinline__ Rule decode(const RawRule<16>& y) {
+  const RuleRec& x = y.w;
+  return Rule{x.lo, x.period, x.c, (int32_t)(x.pd & 0xFFFFu), (int32_t)(x.pd >> 16)};
+}
+__device__ __forceinline__ Rule decode(const RawRule<8>& y) {
+  const uint2 x = y.w;
+  const uint32_t per = x.x >> 24;
+  return Rule{per == R8_DEAD ? -1 : (int32_t)(x.x & 0xFFFFFFu), per == R8_DEAD ? 0 : (int32_t)per,
+              (int32_t)(x.y & 0xFFFFu), (int32_t)((x.y >> 16) & 0xFFu), (int32_t)(x.y >> 24)};
+}
+
+template <int RB>
+__device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
+  return decode(load_raw<RB>(s, slot));
+}
+
+// Rule records of one neuron kept in registers before its selection.
+template <int RB>
+constexpr int kPrefetch = RB == 8 ? 4 : 2;
 
 __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   if (r.period == 0) return n == r.lo;
@@ -62,29 +82,56 @@ __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   return ((uint32_t)(n - r.lo) % (uint32_t)r.period) == 0u;
 }
 
-// Rule chosen by open neuron i holding n spikes at step k, or -1.  `first`
-// is the already loaded record of slot r0 (valid if r0 < r1).
+// What a neuron needs to take its step, loaded ahead of its use.  The rule
+// records are named fields (not an array) so that they stay in registers.
 template <int RB>
-__device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64_t k, int32_t n,
-                                               int32_t r0, int32_t r1, const Rule& first) {
-  if (r0 >= r1) return -1;
+struct NeuronIn {
+  int32_t C;        // C_k (after reception)
+  uint32_t meta;    // D_k and reception flag
+  int32_t r0, r1;   // rule slots
+  int32_t pend;     // pending slot (STANDARD, D_k == 1)
+  // open neuron: records of slots r0 .. r0 + kPrefetch - 1 (those below r1);
+  // neuron opening now (STANDARD): p0 = record of the pending slot
+  RawRule<RB> p0, p1, p2, p3;
+};
+
+template <int X, int RB>
+__device__ __forceinline__ const RawRule<RB>& pf_at(const NeuronIn<RB>& in) {
+  if constexpr (X == 0) return in.p0;
+  else if constexpr (X == 1) return in.p1;
+  else if constexpr (X == 2) return in.p2;
+  else return in.p3;
+}
+
+// Rule chosen by open neuron i holding n = in.C spikes at step k, or -1.
+template <int RB>
+__device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64_t k,
+                                               const NeuronIn<RB>& in) {
+  constexpr int PF = kPrefetch<RB>;
+  const int32_t n = in.C, r0 = in.r0, r1 = in.r1;
+#define SNP_APPLIES(X) (X < PF && r0 + X < r1 && rule_applies(decode(pf_at<X, RB>(in)), n))
   if (s.sel == SEL_FIRST) {
-    if (rule_applies(first, n)) return r0;
-    for (int32_t r = r0 + 1; r < r1; ++r)
+    if (SNP_APPLIES(0)) return r0;
+    if (SNP_APPLIES(1)) return r0 + 1;
+    if (SNP_APPLIES(2)) return r0 + 2;
+    if (SNP_APPLIES(3)) return r0 + 3;
+    for (int32_t r = r0 + PF; r < r1; ++r)
       if (rule_applies(load_rule<RB>(s, r), n)) return r;
     return -1;
   }
-  uint32_t cnt = rule_applies(first, n) ? 1u : 0u;
-  for (int32_t r = r0 + 1; r < r1; ++r) cnt += rule_applies(load_rule<RB>(s, r), n) ? 1u : 0u;
+  const bool a0 = SNP_APPLIES(0), a1 = SNP_APPLIES(1), a2 = SNP_APPLIES(2), a3 = SNP_APPLIES(3);
+#undef SNP_APPLIES
+  uint32_t cnt = (uint32_t)a0 + (uint32_t)a1 + (uint32_t)a2 + (uint32_t)a3;
+  for (int32_t r = r0 + PF; r < r1; ++r) cnt += rule_applies(load_rule<RB>(s, r), n) ? 1u : 0u;
   if (cnt == 0) return -1;
   const uint64_t key = ((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)i;
   const uint64_t h = mix64(mix64(s.seed) ^ key);
   uint32_t j = (uint32_t)(((h >> 32) * (uint64_t)cnt) >> 32);
-  if (rule_applies(first, n)) {
-    if (j == 0) return r0;
-    --j;
-  }
-  for (int32_t r = r0 + 1; r < r1; ++r) {
+  if (a0) { if (j == 0) return r0; --j; }
+  if (a1) { if (j == 0) return r0 + 1; --j; }
+  if (a2) { if (j == 0) return r0 + 2; --j; }
+  if (a3) { if (j == 0) return r0 + 3; --j; }
+  for (int32_t r = r0 + PF; r < r1; ++r) {
     if (rule_applies(load_rule<RB>(s, r), n)) {
       if (j == 0) return r;
       --j;
@@ -159,32 +206,28 @@ __device__ __forceinline__ bool step_prologue(const SysDev& s, int32_t tile, int
   return true;
 }
 
-// What a neuron needs to take its step, loaded ahead of its use.
-struct NeuronIn {
-  int32_t C;        // C_k (after reception)
-  uint32_t meta;    // D_k and reception flag
-  int32_t r0, r1;   // rule slots
-  int32_t pend;     // pending slot (STANDARD, D_k == 1)
-  Rule rec;         // open neuron: record of slot r0 (if r0 < r1);
-                    // neuron opening now (STANDARD): record of the pending slot
-};
-
 template <int RB>
 __device__ __forceinline__ void prefetch_neuron(const SysDev& s, int32_t i, uint32_t meta,
-                                                NeuronIn& in) {
+                                                NeuronIn<RB>& in) {
+  constexpr int PF = kPrefetch<RB>;
   in.meta = meta;
   in.r0 = s.rs[i];
   in.r1 = s.rs[i + 1];
   const int32_t D = (int32_t)(meta & META_D);
-  in.pend = -1;
-  int32_t slot = -1;
-  if (D == 0) {
-    if (in.r0 < in.r1) slot = in.r0;
-  } else if (D == 1 && s.sem == SEM_STANDARD) {
-    in.pend = s.pend[i];
-    slot = in.pend;
+  const bool open = D == 0;
+  in.pend = (D == 1 && s.sem == SEM_STANDARD) ? s.pend[i] : -1;
+  // every record is loaded from a valid slot (slot 0 stands in for unused
+  // ones and stays in cache), so the fields are always written
+  const int32_t s0 = open ? (in.r0 < in.r1 ? in.r0 : 0) : (in.pend >= 0 ? in.pend : 0);
+  in.p0 = load_raw<RB>(s, s0);
+  in.p1 = load_raw<RB>(s, (PF > 1 && open && in.r0 + 1 < in.r1) ? in.r0 + 1 : 0);
+  if constexpr (PF > 2) {
+    in.p2 = load_raw<RB>(s, (open && in.r0 + 2 < in.r1) ? in.r0 + 2 : 0);
+    in.p3 = load_raw<RB>(s, (open && in.r0 + 3 < in.r1) ? in.r0 + 3 : 0);
+  } else {
+    in.p2 = in.p1;
+    in.p3 = in.p1;
   }
-  if (slot >= 0) in.rec = load_rule<RB>(s, slot);
 }
 
 // Selection + delay bookkeeping of neuron i.  Writes the neuron's state and
@@ -198,28 +241,24 @@ struct Sel {
 
 template <int RB, bool CNT>
 __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k,
-                                             const NeuronIn& in, Cnt& cnt) {
+                                             const NeuronIn<RB>& in, Cnt& cnt) {
   const int32_t D = (int32_t)(in.meta & META_D);
   int32_t Dn = 0, cons = 0, sel = -1;
   Sel o{0, -1, false};
   if (D == 0) {
-    sel = choose_rule<RB>(s, i, k, in.C, in.r0, in.r1, in.rec);
+    sel = choose_rule<RB>(s, i, k, in);
     if (CNT) {
       cnt.v[C_OPEN] += 1;
       cnt.v[C_RULES] += (unsigned long long)(in.r1 - in.r0);
     }
     if (sel >= 0) {
-      int32_t rc, rp, rd;
-      if (sel == in.r0) {
-        rc = in.rec.c;
-        rp = in.rec.p;
-        rd = in.rec.d;
-      } else {
-        const Rule r = load_rule<RB>(s, sel);
-        rc = r.c;
-        rp = r.p;
-        rd = r.d;
-      }
+      const int32_t x = sel - in.r0;
+      const Rule r = x == 0 ? decode(in.p0)
+                   : x == 1 ? decode(in.p1)
+                   : (x == 2 && kPrefetch<RB> > 2) ? decode(in.p2)
+                   : (x == 3 && kPrefetch<RB> > 3) ? decode(in.p3)
+                   : load_rule<RB>(s, sel);
+      const int32_t rc = r.c, rp = r.p, rd = r.d;
       cons = rc;
       Dn = rd;
       if (s.sem == SEM_PAPER || rd == 0) {
@@ -237,7 +276,7 @@ __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t
     if (CNT && Dn == 0) cnt.v[C_REOPEN] += 1;
     if (s.sem == SEM_STANDARD && Dn == 0) {
       o.erule = in.pend;
-      o.emit = in.rec.p;
+      o.emit = decode(in.p0).p;
     }
   }
   const uint32_t rf = (s.sem == SEM_PAPER) ? (D == 0 ? 1u : 0u) : (Dn == 0 ? 1u : 0u);

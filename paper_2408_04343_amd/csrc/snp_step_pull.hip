@@ -36,7 +36,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   const int32_t t0 = tile * PULL_TILE;
   const int tid = threadIdx.x;
 
-  NeuronIn in[PULL_NPT];
+  NeuronIn<RB> in[PULL_NPT];
 #pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
     const int32_t t = t0 + tid + r * PULL_NT;

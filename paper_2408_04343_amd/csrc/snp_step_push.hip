@@ -21,7 +21,7 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
   unsigned long long dig = 0;
   Sel o{0, -1, false};
   if (i < s.q) {
-    NeuronIn in;
+    NeuronIn<RB> in;
     prefetch_neuron<RB>(s, i, s.meta[i], in);
     int32_t C = s.C[i];
     if (k > 0) {
