@@ -207,6 +207,38 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     return out
 
 
+def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optimized", "csr_push")):
+    """Config 3: 4,194,304 neurons, power-law out-degree (exponent 2.1, 1..4,096),
+    in-degree hubs, hash choice, 500 steps.  ELL is reported analytically (its
+    padded matrix, (z+1) x m pairs, exceeds the device memory)."""
+    from paper_2408_04343_amd import workloads as wl
+    t0 = time.time()
+    spec = wl.config3(steps=steps)
+    gen_s = time.time() - t0
+    z = spec.max_outdeg()
+    out = {"workload": "config3-skewed: 4,194,304 neurons, power-law out-degree (2.1, max %d), "
+                       "in-degree hubs, 1-4 rules, delays 0..5, hash choice" % z,
+           "q": spec.q, "rules": spec.m, "synapses": spec.nnz, "max_out_degree": z,
+           "gen_s": round(gen_s, 1),
+           "ell_bytes_analytic": 8 * (z + 1) * spec.m,
+           "optimized_bytes_analytic": 4 * z * spec.q, "layouts": {}}
+    for lay in layouts:
+        try:
+            r = run_layout(binding, torch, spec, lay, steps, warmup, 64)
+        except binding.SnpError as e:
+            out["layouts"][lay] = {"error": str(e)}
+            log("config3 %s: %s" % (lay, e))
+            continue
+        b, _cnt = count_bytes(binding, spec, lay, min(steps, 200), warmup, r["info"])
+        r["alg_bytes_per_step"] = b
+        r["alg_GBps"] = b / (r["ms_per_step"] * 1e-3) / 1e9
+        r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+        out["layouts"][lay] = {k: v for k, v in r.items() if k != "info"}
+        log("config3 %-10s %.4f ms/step  %.3e nu/s  %.0f GB/s alg" %
+            (lay, r["ms_per_step"], r["neuron_updates_per_s"], r["alg_GBps"]))
+    return out
+
+
 def cpu_baseline(spec, seconds):
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
@@ -276,6 +308,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--skewed", action="store_true", help="also measure the skewed-degree workload")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
@@ -328,6 +361,7 @@ def main():
     batched = None
     if not args.no_batch:
         batched = run_batched(binding, torch, scale=args.batch_scale)
+    skewed = run_skewed(binding, torch) if args.skewed else None
     served = None
     if not args.no_serve:
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
@@ -350,6 +384,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_vs_plain": batched,
         "served": served,
+        "skewed": skewed,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
                                 "over": "graph chunks of %d steps" % args.chunk},
         "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()
