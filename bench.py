@@ -252,7 +252,8 @@ def cpu_baseline(spec, seconds):
             "sample": "%s: first %d steps, single-threaded C oracle (%.1f s)" % (spec.name, n, dt)}
 
 
-KERNEL_SOURCES = ["paper_2408_04343_amd/csrc/snp_step_pull.hip", "paper_2408_04343_amd/csrc/snp_device.h",
+KERNEL_SOURCES = ["paper_2408_04343_amd/csrc/snp_step_pull.h", "paper_2408_04343_amd/csrc/snp_step_pull.hip",
+                  "paper_2408_04343_amd/csrc/snp_device.h",
                   "paper_2408_04343_amd/csrc/snp_internal.h"]
 
 
@@ -355,7 +356,9 @@ def main():
         roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(head["frac_of_peak"], 4),
                 "traffic": None if traffic is None else int(traffic),
-                "kernel": "step_pull_kernel" if args.layout == "csr_pull" else "step_push_kernel",
+                "kernel": ("step_pull_kernel" if args.layout == "csr_pull" else
+                           "step_bin_kernel" if head["info"].get("push_mode") == binding.PUSH_BINNED
+                           else "step_push_kernel"),
                 "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
                 "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}
     batched = None

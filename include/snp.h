@@ -82,6 +82,26 @@ extern "C" {
 #define SNP_SEM_PAPER_KERNEL 1
 
 /* flags */
+/* CSR_PULL reception.  STAGED: every block copies the emitted values of
+ * one source chunk at a time into LDS and reads them there (best when a
+ * block's in-edges outnumber the words of the emit vector).  GATHER: every
+ * in-edge reads its source's value from the emit vector in device memory
+ * (best for large, sparse systems, where staging would copy the whole
+ * vector for few edges).  AUTO picks by in-edges per block vs vector size. */
+#define SNP_PULL_AUTO   0
+#define SNP_PULL_STAGED 1
+#define SNP_PULL_GATHER 2
+
+/* Push layouts.  ATOMIC: every synapse of an emitting neuron adds its
+ * spikes to the target's count with a device-wide atomic, as the STEP of
+ * Algorithms 4 and 5 does.  BINNED: the walk over the same layout appends a
+ * record per synapse to a region (source tile -> target tile) and the owner
+ * of the target tile sums them at the next step; no device-wide atomics.
+ * AUTO: BINNED up to 2048 tiles of 4096 neurons, ATOMIC above.             */
+#define SNP_PUSH_AUTO   0
+#define SNP_PUSH_ATOMIC 1
+#define SNP_PUSH_BINNED 2
+
 #define SNP_F_DIGEST   0x1u /* keep a digest of every reached state          */
 #define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
 #define SNP_F_NO_GRAPH 0x4u /* launch step kernels one by one (no hipGraph)  */
@@ -105,6 +125,10 @@ typedef struct snp_opts {
   int64_t ring;        /* entries kept by the digest / counter rings; 0 = 4096 */
   int32_t emit_bits;   /* CSR_PULL: bits per emitted value (1, 2, 4, 8, 16);
                           0 = the smallest that holds every p               */
+  int32_t pull_mode;   /* CSR_PULL: how a block reads the emitted values of
+                          its sources, SNP_PULL_* (0 = AUTO)                */
+  int32_t push_mode;   /* OPTIMIZED / ELL / CSR_PUSH: how spikes reach their
+                          targets, SNP_PUSH_* (0 = AUTO)                    */
   snp_alloc_fn alloc;
   snp_free_fn free;
   void* alloc_ctx;
@@ -230,7 +254,9 @@ typedef struct snp_info_t {
   int32_t pull_tile_log2;/* CSR_PULL: log2 of the neurons per block          */
   int32_t pull_chunk;    /* CSR_PULL: sources per LDS chunk                  */
   int32_t pull_chunks;   /* CSR_PULL: number of source chunks                */
-  int32_t pad;
+  int32_t pull_mode;     /* CSR_PULL: SNP_PULL_STAGED or SNP_PULL_GATHER     */
+  int32_t push_mode;     /* push layouts: SNP_PUSH_ATOMIC or SNP_PUSH_BINNED */
+  int32_t reserved;
   int64_t device_bytes;  /* device memory held by the handle                 */
 } snp_info_t;
 int snp_info(snp_sys* sys, snp_info_t* out);
@@ -271,8 +297,9 @@ int snp_set_step_limit(snp_sys* sys, int64_t limit);
  * every tile of every member, each member keeps its own step index, HASH
  * key, halting flag and step limit, so a member's computation is the same
  * as when it runs alone.  Members must share layout, rule record size,
- * emit width, pull tile size and SNP_F_DIGEST / SNP_F_COUNTERS flags
- * (SNP_ENOTSUP otherwise).  While in a batch a handle refuses snp_step,
+ * emit width and SNP_F_DIGEST / SNP_F_COUNTERS flags (SNP_ENOTSUP
+ * otherwise); members of both reception modes (SNP_PULL_* / SNP_PUSH_*) may
+ * mix, at one launch per mode and step.  While in a batch a handle refuses snp_step,
  * snp_write_state and snp_destroy (SNP_EBUSY); its read calls work.      */
 typedef struct snp_batch snp_batch;
 

@@ -25,6 +25,10 @@ LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL
            "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL}
 SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
 SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
+PULL_AUTO, PULL_STAGED, PULL_GATHER = 0, 1, 2
+PULL_MODES = {"auto": PULL_AUTO, "staged": PULL_STAGED, "gather": PULL_GATHER}
+PUSH_AUTO, PUSH_ATOMIC, PUSH_BINNED = 0, 1, 2
+PUSH_MODES = {"auto": PUSH_AUTO, "atomic": PUSH_ATOMIC, "binned": PUSH_BINNED}
 
 # exported symbols, in header order
 SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_read_config",
@@ -44,7 +48,7 @@ class Opts(ct.Structure):
     _fields_ = [("layout", ct.c_int32), ("select", ct.c_int32), ("semantics", ct.c_int32),
                 ("chunk", ct.c_int32), ("seed", ct.c_uint64), ("stream", ct.c_void_p),
                 ("flags", ct.c_uint32), ("device", ct.c_int32), ("ring", ct.c_int64),
-                ("emit_bits", ct.c_int32),
+                ("emit_bits", ct.c_int32), ("pull_mode", ct.c_int32), ("push_mode", ct.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ct.c_void_p)]
 
 
@@ -70,7 +74,8 @@ class Info(ct.Structure):
     _fields_ = [("q", ct.c_int32), ("m", ct.c_int32), ("nsyn", ct.c_int64), ("zmax", ct.c_int32),
                 ("layout", ct.c_int32), ("rule_bytes", ct.c_int32), ("emit_bits", ct.c_int32),
                 ("pull_tile_log2", ct.c_int32), ("pull_chunk", ct.c_int32),
-                ("pull_chunks", ct.c_int32), ("pad", ct.c_int32), ("device_bytes", ct.c_int64)]
+                ("pull_chunks", ct.c_int32), ("pull_mode", ct.c_int32), ("push_mode", ct.c_int32),
+                ("reserved", ct.c_int32), ("device_bytes", ct.c_int64)]
 
 
 class SnpError(RuntimeError):
@@ -201,7 +206,7 @@ class System:
     def __init__(self, q, spikes0, rules, src, dst, *, layout="auto", select="first",
                  semantics="standard", seed=0, chunk=64, digest=False, counters=False,
                  graph=True, ring=0, device=None, memory="auto", stream=None, emit_bits=0,
-                 wide_rules=False):
+                 wide_rules=False, pull_mode="auto", push_mode="auto"):
         self._h = ct.c_void_p()
         self.q = int(q)
         s0 = _i32(spikes0)
@@ -221,6 +226,8 @@ class System:
                    (0 if graph else F_NO_GRAPH) | (F_WIDE_RULES if wide_rules else 0))
         o.ring = int(ring)
         o.emit_bits = int(emit_bits)
+        o.pull_mode = PULL_MODES[pull_mode] if isinstance(pull_mode, str) else int(pull_mode)
+        o.push_mode = PUSH_MODES[push_mode] if isinstance(push_mode, str) else int(push_mode)
         o.device = -1 if device is None else int(device)
         torch = _torch_cuda()
         self._torch_stream = None
@@ -337,7 +344,7 @@ class System:
     def info(self):
         i = Info()
         _check(lib.snp_info(self._h, ct.byref(i)))
-        return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "pad"}
+        return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "reserved"}
 
     def clone(self, seed=None, spikes0=None, stream=None):
         """A new system sharing this one's rules and synapses on the device."""

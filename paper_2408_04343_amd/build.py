@@ -9,7 +9,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsnp.so")
-SOURCES = ["snp_api.hip", "snp_batch.hip", "snp_kernels.hip", "snp_step_pull.hip", "snp_step_push.hip"]
+SOURCES = ["snp_api.hip", "snp_batch.hip", "snp_kernels.hip", "snp_step_pull.hip", "snp_step_pull_gather.hip",
+           "snp_step_bin.hip",
+           "snp_step_push.hip"]
 ARCH = os.environ.get("SNP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -64,6 +64,20 @@ int32_t pull_chunk_sources(int32_t w, int32_t tb) {
   return (int32_t)std::max<int64_t>(128, src);
 }
 
+// Sources per chunk when values are read from device memory: only the
+// record encoding bounds it.
+int32_t pull_gather_chunk(int32_t tb) { return (int32_t)((1LL << (32 - tb)) - 128); }
+
+// AUTO: staging copies the whole emit vector into every block, gathering
+// costs one scattered load per in-edge; gather when a block's in-edges are
+// fewer than half the words of the emit vector.
+bool pull_gathers(int32_t mode, int32_t q, int64_t nsyn, int32_t w) {
+  if (mode != SNP_PULL_AUTO) return mode == SNP_PULL_GATHER;
+  const int64_t tiles = ((int64_t)q + (1LL << PULL_TB_STAGED) - 1) >> PULL_TB_STAGED;
+  const int64_t words = ((int64_t)q * w + 31) / 32;
+  return 2 * (nsyn / tiles) < words;
+}
+
 struct Plan {
   int64_t bytes = 0;
   void add(int64_t b) { bytes += (b + 255) / 256 * 256; }
@@ -71,7 +85,7 @@ struct Plan {
 
 // Device bytes of a system; mirrors the allocations of snp_create.
 int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout, uint32_t flags,
-                   int64_t ring, int32_t emit_w, int32_t tb) {
+                   int64_t ring, int32_t emit_w, int32_t gather) {
   Plan p;
   p.add(4LL * q);            // C
   p.add(4LL * q);            // meta
@@ -87,19 +101,35 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
   if (flags & SNP_F_DIGEST) p.add(8 * ring);
   if (flags & SNP_F_COUNTERS) p.add(8LL * NCOUNT * (ring + 1));
   if (layout == L_CSR_PULL) {
-    const int64_t tile = 1LL << tb;
-    const int64_t tiles = (q + tile - 1) / tile;
-    const int64_t nc = (q + pull_chunk_sources(emit_w, tb) - 1) / pull_chunk_sources(emit_w, tb);
+    // the larger of the two reception modes unless the mode is given
+    int64_t best = 0;
+    for (int g = 0; g < 2; ++g) {
+      if (gather >= 0 && g != gather) continue;
+      const int32_t tb = g ? PULL_TB_GATHER : PULL_TB_STAGED;
+      const int64_t tile = 1LL << tb;
+      const int64_t tiles = (q + tile - 1) / tile;
+      const int64_t cs = g ? pull_gather_chunk(tb) : pull_chunk_sources(emit_w, tb);
+      const int64_t nc = (q + cs - 1) / cs;
+      Plan x;
+      x.add(4LL * (std::max<int64_t>(nnz, 1) + 3 * tiles * nc + 4));   // blocked in-edges (padded)
+      x.add(4LL * (tiles * nc + 1));
+      x.add(2 * tiles * tile * emit_w / 32 * 4);
+      best = std::max(best, x.bytes);
+    }
+    p.bytes += best;
     p.add(4LL * (q + 1));
     p.add(4LL * std::max<int64_t>(nnz, 1));
-    p.add(4LL * (std::max<int64_t>(nnz, 1) + 3 * tiles * nc + 4));   // blocked in-edges (padded)
-    p.add(4LL * (tiles * nc + 1));
-    p.add(2 * tiles * tile * emit_w / 32 * 4);
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
   } else {
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
     p.add(4LL * q * 2);      // delta[2]
     p.add(4LL * (q + 1));    // out_ptr
+    const int64_t nb = (q + (1LL << BIN_TB) - 1) >> BIN_TB;
+    if (nb <= BIN_MAX_TILES) {  // binned push: bins, counts, region offsets
+      p.add(4LL * std::max<int64_t>(nnz, 1));
+      p.add(4LL * std::max<int64_t>(nnz, 1));
+      for (int x = 0; x < 4; ++x) p.add(4LL * nb * nb);
+    }
     p.add(4LL * std::max<int64_t>(nnz, 1));
     if (layout == L_OPT) p.add(4LL * z * q);
     if (layout == L_ELL) p.add(8LL * (z + 1) * std::max(m, 1));
@@ -171,6 +201,8 @@ int query(snp_sys* s, StateInfo* si) {
 // overflow of the reception not yet folded into C (sets si->overflow).
 int materialize(snp_sys* s, StateInfo* si) {
   const int32_t q = s->q;
+  if (s->d.layout != L_CSR_PULL && s->d.push_binned && si->rbuf >= 0)
+    HIPCHK(launch_bin_gather(s->d, si->rbuf, si->rbuf ? s->d.delta[1] : s->d.delta[0], s->stream));
   HIPCHK(launch_materialize(s->d, si->rbuf, si->sbuf, s->scratch, s->scratch + q,
                             s->scratch + 2 * (size_t)q, s->scratch + 3 * (size_t)q, s->stream));
   int32_t ov = 0;
@@ -257,6 +289,16 @@ int alloc_state(snp_sys* s, const int32_t* spikes0) {
   } else {
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return st;
+    d.bins[0] = d.bins[1] = nullptr;
+    d.bcnt[0] = d.bcnt[1] = nullptr;
+    if (d.push_binned) {
+      const size_t nb2 = (size_t)d.bnb * (size_t)d.bnb;
+      for (int b = 0; b < 2; ++b) {
+        d.bins[b] = (uint32_t*)s->dalloc(4 * (size_t)std::max<int64_t>(s->nnz, 1));
+        if (!d.bins[b]) return fail(SNP_ENOMEM, "device allocation failed");
+        if ((st = alloc_fill(s, (void**)&d.bcnt[b], 4 * nb2, 0)) != SNP_OK) return st;
+      }
+    }
   }
   return SNP_OK;
 }
@@ -305,7 +347,7 @@ int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layo
   if (q < 1 || m < 0 || nsyn < 0 || zmax < 0 || !bytes) return fail(SNP_EINVAL, "bad shape");
   if (layout == SNP_LAYOUT_AUTO) layout = SNP_LAYOUT_CSR_PULL;
   if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
-  *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16, 12);
+  *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16, -1);
   return SNP_OK;
 }
 
@@ -324,6 +366,8 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   if (o.layout == SNP_LAYOUT_AUTO) o.layout = SNP_LAYOUT_CSR_PULL;
   if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
   if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
+  if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_GATHER) return fail(SNP_EINVAL, "bad pull_mode");
+  if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_BINNED) return fail(SNP_EINVAL, "bad push_mode");
   if (o.semantics != SNP_SEM_STANDARD && o.semantics != SNP_SEM_PAPER_KERNEL)
     return fail(SNP_EINVAL, "bad semantics");
   if (o.chunk <= 0) o.chunk = kDefaultChunk;
@@ -485,8 +529,9 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     if (o.emit_bits < d.emit_w) return bail(fail(SNP_EINVAL, "emit_bits too small for the largest p"));
     d.emit_w = o.emit_bits;
   }
-  d.pull_tb = 12;
-  d.pull_chunk = pull_chunk_sources(d.emit_w, d.pull_tb);
+  d.pull_gather = pull_gathers(o.pull_mode, q, nsyn, d.emit_w) ? 1 : 0;
+  d.pull_tb = d.pull_gather ? PULL_TB_GATHER : PULL_TB_STAGED;
+  d.pull_chunk = d.pull_gather ? pull_gather_chunk(d.pull_tb) : pull_chunk_sources(d.emit_w, d.pull_tb);
 
   int st;
   {
@@ -582,6 +627,31 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       for (int64_t e = 0; e < nsyn; ++e) indeg[oc[e]]++;
       if ((st = upload(s, &p, indeg.data(), (size_t)q)) != SNP_OK) return bail(st);
       d.in_deg = p;
+    }
+    const int64_t nb = ((int64_t)q + (1LL << BIN_TB) - 1) >> BIN_TB;
+    if (o.push_mode == SNP_PUSH_BINNED && nb > BIN_MAX_TILES)
+      return bail(fail(SNP_ENOTSUP, "binned push: more than 2048 tiles of 4096 neurons"));
+    d.push_binned = (o.push_mode == SNP_PUSH_BINNED || (o.push_mode == SNP_PUSH_AUTO && nb <= BIN_MAX_TILES)) ? 1 : 0;
+    d.bnb = d.push_binned ? (int32_t)nb : 0;
+    if (d.push_binned) {
+      // region (b -> t) holds one slot per synapse from tile b into tile t;
+      // regions are laid out target-major, so a tile's inbox is contiguous
+      std::vector<int32_t> cap((size_t)(nb * nb), 0);
+      for (int32_t i = 0; i < q; ++i)
+        for (int32_t e = op[i]; e < op[(size_t)i + 1]; ++e)
+          cap[(size_t)((oc[e] >> BIN_TB) * nb + (i >> BIN_TB))]++;   // [t][b]
+      std::vector<int32_t> offc((size_t)(nb * nb)), offp((size_t)(nb * nb));
+      int64_t run = 0;
+      for (int64_t t = 0; t < nb; ++t)
+        for (int64_t b = 0; b < nb; ++b) {
+          offc[(size_t)(t * nb + b)] = (int32_t)run;
+          offp[(size_t)(b * nb + t)] = (int32_t)run;
+          run += cap[(size_t)(t * nb + b)];
+        }
+      if ((st = upload(s, &p, offc.data(), offc.size())) != SNP_OK) return bail(st);
+      d.boff = p;
+      if ((st = upload(s, &p, offp.data(), offp.size())) != SNP_OK) return bail(st);
+      d.boffp = p;
     }
     if ((st = upload(s, &p, op.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
     d.out_ptr = p;
@@ -749,6 +819,8 @@ int snp_read_counters(snp_sys* s, snp_counters* out, int64_t first, int64_t coun
   if (first + count == si.steps && si.steps == si.kx) {
     // the reception of the last executed step is still pending: count it now
     HIPCHK(hipMemsetAsync(s->dig_tmp, 0, 24, s->stream));
+    if (s->d.layout != L_CSR_PULL && s->d.push_binned && si.rbuf >= 0)
+      HIPCHK(launch_bin_gather(s->d, si.rbuf, si.rbuf ? s->d.delta[1] : s->d.delta[0], s->stream));
     HIPCHK(launch_recv_counts(s->d, si.rbuf, s->dig_tmp, s->stream));
     HIPCHK(hipMemcpyAsync(tail, s->dig_tmp, 24, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -817,6 +889,9 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
     for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.emit[b], 0, 4 * words, s->stream));
   } else {
     for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.delta[b], 0, 4 * (size_t)q, s->stream));
+    if (s->d.push_binned)
+      for (int b = 0; b < 2; ++b)
+        HIPCHK(hipMemsetAsync(s->d.bcnt[b], 0, 4 * (size_t)s->d.bnb * (size_t)s->d.bnb, s->stream));
   }
   Ctl c;
   std::memset(&c, 0, sizeof(c));
@@ -883,6 +958,9 @@ int snp_info(snp_sys* s, snp_info_t* o) {
   o->pull_tile_log2 = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_tb : 0;
   o->pull_chunk = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_chunk : 0;
   o->pull_chunks = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_nc : 0;
+  o->pull_mode = s->layout != SNP_LAYOUT_CSR_PULL ? 0 : s->d.pull_gather ? SNP_PULL_GATHER : SNP_PULL_STAGED;
+  o->push_mode = s->layout == SNP_LAYOUT_CSR_PULL ? 0 : s->d.push_binned ? SNP_PUSH_BINNED : SNP_PUSH_ATOMIC;
+  o->reserved = 0;
   o->device_bytes = s->device_bytes;
   return SNP_OK;
 }

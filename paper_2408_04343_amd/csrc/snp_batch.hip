@@ -1,9 +1,11 @@
 // Batched form of the step: many independent systems advanced by one launch
-// per step.  The members' descriptors and a tile table (block -> member,
-// block within the member) live in device memory; launches are captured in
-// graphs sized by capacity, so adding or removing members only rewrites the
-// tables.  Each member keeps its own control block (step index, halting,
-// step limit), which makes its computation independent of the batch.
+// per step and reception mode.  The members' descriptors and a tile table per
+// mode (block -> member, block within the member) live in device memory;
+// launches are captured in graphs sized by capacity, so adding or removing
+// members only rewrites the tables.  Each member keeps its own control block
+// (step index, halting, step limit), which makes its computation independent
+// of the batch.  Group 0 holds the staged pull / atomic push members, group 1
+// the gather pull / binned push ones (different kernels and tile sizes).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -29,21 +31,22 @@ struct snp_batch {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<snp_sys*> members;
-  SysDev proto{};
-  bool has_proto = false;
+  SysDev proto[2]{};            // first member of each group: picks the kernel
+  bool has_proto[2] = {false, false};
   // device tables
   SysDev* d_members = nullptr;
-  int2* d_tiles = nullptr;
-  int32_t* d_counts = nullptr;  // [0] members (advance, status), [1] tiles (step launches)
+  int2* d_tiles = nullptr;      // group g at [g * cap_tiles, (g + 1) * cap_tiles)
+  int32_t* d_counts = nullptr;  // [0] members (advance, status), [1 + g] tiles of group g
   int64_t* d_steps = nullptr;
   int32_t* d_done = nullptr;
   int32_t cap_members = 0, cap_tiles = 0;
-  int32_t ntiles = 0;
-  size_t lds = 0;
+  int32_t ntiles[2] = {0, 0};
+  size_t lds[2] = {0, 0};
   // captured chunk
   hipGraphExec_t graph = nullptr;
   int32_t graph_cap_members = 0, graph_cap_tiles = 0;
-  size_t graph_lds = 0;
+  size_t graph_lds[2] = {0, 0};
+  int graph_groups = 0;         // groups present when the graph was captured
   bool dirty = true;  // tables need uploading
 
   void free_tables() {
@@ -64,9 +67,13 @@ namespace {
 
 bool compatible(const SysDev& a, const SysDev& b) {
   return a.layout == b.layout && a.rule_bytes == b.rule_bytes &&
-         (a.layout != L_CSR_PULL || (a.emit_w == b.emit_w && a.pull_tb == b.pull_tb)) &&
-         a.flags == b.flags;
+         (a.layout != L_CSR_PULL || a.emit_w == b.emit_w) && a.flags == b.flags;
 }
+
+// Group of a member: its reception mode.
+int group_of(const SysDev& d) { return d.layout == L_CSR_PULL ? d.pull_gather : d.push_binned; }
+
+int groups_present(const snp_batch* b) { return (b->has_proto[0] ? 1 : 0) | (b->has_proto[1] ? 2 : 0); }
 
 int ensure_capacity(snp_batch* b, int32_t need_members, int32_t need_tiles) {
   if (need_members <= b->cap_members && need_tiles <= b->cap_tiles && b->d_members) return SNP_OK;
@@ -76,8 +83,8 @@ int ensure_capacity(snp_batch* b, int32_t need_members, int32_t need_tiles) {
   HIPCHK(hipStreamSynchronize(b->stream));
   b->free_tables();
   HIPCHK(hipMalloc(&b->d_members, sizeof(SysDev) * (size_t)cm));
-  HIPCHK(hipMalloc(&b->d_tiles, sizeof(int2) * (size_t)ct));
-  HIPCHK(hipMalloc(&b->d_counts, 2 * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&b->d_tiles, 2 * sizeof(int2) * (size_t)ct));
+  HIPCHK(hipMalloc(&b->d_counts, 3 * sizeof(int32_t)));
   HIPCHK(hipMalloc(&b->d_steps, sizeof(int64_t) * (size_t)cm));
   HIPCHK(hipMalloc(&b->d_done, sizeof(int32_t) * (size_t)cm));
   b->cap_members = cm;
@@ -89,38 +96,47 @@ int ensure_capacity(snp_batch* b, int32_t need_members, int32_t need_tiles) {
 // Rebuilds the member and tile tables and uploads them on the batch stream.
 int upload_tables(snp_batch* b) {
   const int32_t n = (int32_t)b->members.size();
-  int32_t tiles = 0;
-  size_t lds = 0;
+  int32_t tiles[2] = {0, 0};
+  size_t lds[2] = {0, 0};
   for (snp_sys* s : b->members) {
-    tiles += (s->q + step_tile(s->d) - 1) / step_tile(s->d);
-    if (s->d.layout == L_CSR_PULL) lds = std::max(lds, pull_lds_bytes(s->d));
+    const int g = group_of(s->d);
+    tiles[g] += (s->q + step_tile(s->d) - 1) / step_tile(s->d);
+    if (s->d.layout == L_CSR_PULL) lds[g] = std::max(lds[g], pull_lds_bytes(s->d));
+    else if (s->d.push_binned) lds[g] = std::max(lds[g], bin_lds_bytes(s->d));
   }
-  int st = ensure_capacity(b, n, tiles);
+  int st = ensure_capacity(b, n, std::max(tiles[0], tiles[1]));
   if (st != SNP_OK) return st;
   std::vector<SysDev> hm((size_t)std::max(n, 1));
-  std::vector<int2> ht((size_t)std::max(tiles, 1));
-  int32_t t = 0;
+  std::vector<int2> ht[2];
   for (int32_t i = 0; i < n; ++i) {
     hm[i] = b->members[i]->d;
     const int32_t nt = (b->members[i]->q + step_tile(hm[i]) - 1) / step_tile(hm[i]);
-    for (int32_t x = 0; x < nt; ++x) ht[(size_t)t++] = make_int2(i, x);
+    for (int32_t x = 0; x < nt; ++x) ht[group_of(hm[i])].push_back(make_int2(i, x));
   }
   // the host copies stay alive until the stream has consumed them
   HIPCHK(hipStreamSynchronize(b->stream));
   if (n) HIPCHK(hipMemcpyAsync(b->d_members, hm.data(), sizeof(SysDev) * (size_t)n, hipMemcpyHostToDevice, b->stream));
-  if (tiles) HIPCHK(hipMemcpyAsync(b->d_tiles, ht.data(), sizeof(int2) * (size_t)tiles, hipMemcpyHostToDevice, b->stream));
-  const int32_t counts[2] = {n, tiles};
+  for (int g = 0; g < 2; ++g)
+    if (tiles[g])
+      HIPCHK(hipMemcpyAsync(b->d_tiles + (size_t)g * b->cap_tiles, ht[g].data(), sizeof(int2) * (size_t)tiles[g],
+                            hipMemcpyHostToDevice, b->stream));
+  const int32_t counts[3] = {n, tiles[0], tiles[1]};
   HIPCHK(hipMemcpyAsync(b->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice, b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
-  b->ntiles = tiles;
-  b->lds = lds;
+  for (int g = 0; g < 2; ++g) {
+    b->ntiles[g] = tiles[g];
+    b->lds[g] = lds[g];
+  }
   b->dirty = false;
   return SNP_OK;
 }
 
 int launch_chunk_direct(snp_batch* b, int32_t n) {
   for (int32_t j = 0; j < n; ++j)
-    HIPCHK(launch_step_batch(b->proto, b->d_members, b->d_tiles, b->d_counts + 1, b->ntiles, b->lds, j, b->stream));
+    for (int g = 0; g < 2; ++g)
+      if (b->ntiles[g] > 0)
+        HIPCHK(launch_step_batch(b->proto[g], b->d_members, b->d_tiles + (size_t)g * b->cap_tiles,
+                                 b->d_counts + 1 + g, b->ntiles[g], b->lds[g], j, b->stream));
   HIPCHK(launch_advance_batch(b->d_members, b->d_counts, (int32_t)b->members.size(), n, b->stream));
   return SNP_OK;
 }
@@ -139,8 +155,10 @@ void capture(snp_batch* b) {
   }
   bool ok = true;
   for (int32_t j = 0; j < b->opts.chunk && ok; ++j)
-    ok = launch_step_batch(b->proto, b->d_members, b->d_tiles, b->d_counts + 1, b->cap_tiles, b->lds, j,
-                           b->stream) == hipSuccess;
+    for (int g = 0; g < 2 && ok; ++g)
+      if (b->has_proto[g])
+        ok = launch_step_batch(b->proto[g], b->d_members, b->d_tiles + (size_t)g * b->cap_tiles,
+                               b->d_counts + 1 + g, b->cap_tiles, b->lds[g], j, b->stream) == hipSuccess;
   if (ok) ok = launch_advance_batch(b->d_members, b->d_counts, b->cap_members, b->opts.chunk, b->stream) == hipSuccess;
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (!ok || e != hipSuccess || !g) {
@@ -158,18 +176,22 @@ void capture(snp_batch* b) {
   b->graph = ex;
   b->graph_cap_members = b->cap_members;
   b->graph_cap_tiles = b->cap_tiles;
-  b->graph_lds = b->lds;
+  b->graph_lds[0] = b->lds[0];
+  b->graph_lds[1] = b->lds[1];
+  b->graph_groups = groups_present(b);
 }
 
 int add_member(snp_batch* b, snp_sys* s) {
   if (!s) return fail(SNP_EINVAL, "null handle");
   if (s->in_batch) return fail(SNP_EBUSY, "handle already in a batch");
   if (s->dev != b->dev) return fail(SNP_EINVAL, "handle on another device");
-  if (!b->has_proto) {
-    b->proto = s->d;
-    b->has_proto = true;
-  } else if (!compatible(b->proto, s->d)) {
-    return fail(SNP_ENOTSUP, "member differs in layout, rule record size, emit width, tile or flags");
+  const int g = group_of(s->d);
+  const SysDev& any = b->has_proto[0] ? b->proto[0] : b->proto[1];
+  if ((b->has_proto[0] || b->has_proto[1]) && !compatible(any, s->d))
+    return fail(SNP_ENOTSUP, "member differs in layout, rule record size, emit width or flags");
+  if (!b->has_proto[g]) {
+    b->proto[g] = s->d;
+    b->has_proto[g] = true;
   }
   HIPCHK(hipStreamSynchronize(s->stream));
   s->in_batch = 1;
@@ -264,7 +286,8 @@ int snp_batch_step(snp_batch* b, int64_t k) {
   const int32_t K = b->opts.chunk;
   const bool want_graph = k >= K;
   if (want_graph && (!b->graph || b->graph_cap_members != b->cap_members ||
-                     b->graph_cap_tiles != b->cap_tiles || b->graph_lds < b->lds))
+                     b->graph_cap_tiles != b->cap_tiles || b->graph_lds[0] < b->lds[0] ||
+                     b->graph_lds[1] < b->lds[1] || b->graph_groups != groups_present(b)))
     capture(b);
   while (k > 0) {
     if (b->graph && k >= K) {
@@ -295,7 +318,7 @@ int snp_batch_size(snp_batch* b, int32_t* members, int32_t* tiles) {
     if (st != SNP_OK) return st;
   }
   if (members) *members = (int32_t)b->members.size();
-  if (tiles) *tiles = b->ntiles;
+  if (tiles) *tiles = b->ntiles[0] + b->ntiles[1];
   return SNP_OK;
 }
 

@@ -17,6 +17,10 @@ constexpr uint32_t META_RECV = 0x80000000u;
 constexpr uint32_t META_D = 0x7FFFFFFFu;
 constexpr uint16_t S_NONE = 0xFFFFu;
 constexpr int NCOUNT = 10;  // fields of snp_counters
+constexpr int32_t PULL_TB_STAGED = 12;  // log2 neurons per pull tile, staged reception
+constexpr int32_t PULL_TB_GATHER = 10;  // log2 neurons per pull tile, gather reception
+constexpr int32_t BIN_TB = 12;          // log2 neurons per tile of the binned push
+constexpr int32_t BIN_MAX_TILES = 2048; // binned push up to 2048 tiles (8,388,608 neurons)
 
 // One rule of the rule vector RV in neuron order (16 bytes).
 //   Applicability of E = a^base (a^period)* together with n >= c is
@@ -74,6 +78,15 @@ struct SysDev {
   const int32_t* out_col;    // CSR_PUSH: [nnz]
   const int32_t* out_deg;    // counters only: [q]
   const int32_t* in_deg;     // counters only, push layouts: [q]
+  // binned push: spikes travel as records (target offset | value << 12) in
+  // regions (source tile b -> target tile t) of 4096-neuron tiles; a region
+  // holds as many slots as there are synapses from b into t
+  int32_t push_binned;       // 1: binned reception, 0: atomic adds into delta
+  int32_t bnb;               // tiles (at most 2048)
+  uint32_t* bins[2];         // [max(nnz, 1)] records sent at step k, by k & 1
+  int32_t* bcnt[2];          // [bnb][bnb] records in region (b -> t), stored at [t][b], by k & 1
+  const int32_t* boff;       // [bnb][bnb] first slot of region (b -> t), stored at [t][b]
+  const int32_t* boffp;      // [bnb][bnb] the same, stored at [b][t]
   // pull representation
   const int32_t* in_ptr;     // [q+1] in-neighbour lists (reads and counters)
   const int32_t* in_src;     // [nnz], each list in increasing source id
@@ -83,6 +96,7 @@ struct SysDev {
   int32_t pull_chunk;        // sources per LDS chunk
   int32_t pull_nc;           // number of source chunks
   int32_t pull_tb;           // log2 of the neurons per block (tile)
+  int32_t pull_gather;       // 1: read emitted values from device memory (no LDS chunk)
   // bookkeeping
   Ctl* ctl;
   uint64_t* digests;         // ring [ring]
@@ -93,6 +107,10 @@ struct SysDev {
 // Host-side launchers (defined in snp_kernels.hip).
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_pull_gather(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_pull_batch_gather(const SysDev& s, const SysDev* members, const int2* tiles,
+                                         const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                                         hipStream_t st);
 hipError_t launch_step_push(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull_batch(const SysDev& s, const SysDev* members, const int2* tiles,
                                   const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
@@ -100,6 +118,13 @@ hipError_t launch_step_pull_batch(const SysDev& s, const SysDev* members, const 
 hipError_t launch_step_push_batch(const SysDev& s, const SysDev* members, const int2* tiles,
                                   const int32_t* ntiles, int32_t grid, int32_t j, hipStream_t st);
 int32_t push_tile();
+hipError_t launch_step_bin(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_bin_batch(const SysDev& s, const SysDev* members, const int2* tiles,
+                                 const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                                 hipStream_t st);
+// Sums the records of buffer rbuf per target into out[q] (binned push).
+hipError_t launch_bin_gather(const SysDev& s, int32_t rbuf, int32_t* out, hipStream_t st);
+size_t bin_lds_bytes(const SysDev& s);
 hipError_t launch_advance(Ctl* ctl, int32_t n, hipStream_t st);
 // Batched form: one launch steps every member; `proto` supplies the shared
 // kernel choice (layout, widths, flags), `members`/`tiles`/`ntiles` live in

@@ -29,7 +29,8 @@ namespace snp {
 // ------------------------------------------------------------- dispatch --
 
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st) {
-  return s.layout == L_CSR_PULL ? launch_step_pull(s, j, st) : launch_step_push(s, j, st);
+  if (s.layout == L_CSR_PULL) return launch_step_pull(s, j, st);
+  return s.push_binned ? launch_step_bin(s, j, st) : launch_step_push(s, j, st);
 }
 
 hipError_t launch_step_batch(const SysDev& proto, const SysDev* members, const int2* tiles,
@@ -38,6 +39,7 @@ hipError_t launch_step_batch(const SysDev& proto, const SysDev* members, const i
   if (grid <= 0) return hipSuccess;
   if (proto.layout == L_CSR_PULL)
     return launch_step_pull_batch(proto, members, tiles, ntiles, grid, lds, j, st);
+  if (proto.push_binned) return launch_step_bin_batch(proto, members, tiles, ntiles, grid, lds, j, st);
   return launch_step_push_batch(proto, members, tiles, ntiles, grid, j, st);
 }
 
@@ -96,7 +98,10 @@ hipError_t launch_batch_status(const SysDev* members, const int32_t* nmembers, i
   return hipGetLastError();
 }
 
-int32_t step_tile(const SysDev& s) { return s.layout == L_CSR_PULL ? (1 << s.pull_tb) : push_tile(); }
+int32_t step_tile(const SysDev& s) {
+  if (s.layout == L_CSR_PULL) return 1 << s.pull_tb;
+  return s.push_binned ? (1 << BIN_TB) : push_tile();
+}
 
 // ------------------------------------------------------- reading state --
 

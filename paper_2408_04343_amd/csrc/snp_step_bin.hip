@@ -1,0 +1,447 @@
+// Binned push form of the step (OPTIMIZED, ELL, CSR_PUSH layouts) for gfx950.
+//
+// The STEP of Algorithms 4 and 5 adds, for every emitting rule or neuron, its
+// spikes into the configuration of each target with atomics (Sec. 5).  Here a
+// block owns a tile of 4096 neurons and walks the same layouts (ELL columns,
+// Sy columns, CSR rows) for its emitting neurons, but instead of an atomic per
+// synapse it appends a 4-byte record (target offset | value << 12) to the
+// region (own tile -> target tile) of a bin buffer; slots come from LDS
+// counters, and every region has one slot per synapse, so it never fills up.
+// At the next step the owner of each target tile sums the records addressed
+// to it in LDS.  No global atomics; the sum per target equals the paper's.
+#include "snp_device.h"
+
+namespace snp {
+
+constexpr int BIN_TILE = 1 << BIN_TB;
+constexpr int BIN_NPT = 4;                      // neurons per thread
+constexpr int BIN_NT = BIN_TILE / BIN_NPT;      // 1024 threads
+constexpr int BIN_LIGHT = 64;                   // synapses a thread walks alone
+constexpr int BIN_ROWS = 8;                     // row entries loaded together
+constexpr int BIN_HMAX = 1024;                  // heavy neurons shared by the block
+
+// Exclusive prefix sum of v over the block; *total = the sum of all v.
+template <int NT>
+__device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* wsum, int32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t a = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      const int32_t t = wsum[w];
+      wsum[w] = a;
+      a += t;
+    }
+    wsum[NT / 64] = a;
+  }
+  __syncthreads();
+  *total = wsum[NT / 64];
+  return wsum[wv] + x - v;
+}
+
+// LDS of one block: acc[4096] | pos[nb+1] | roff[nb] | offp[nb] | lcnt[nb] |
+// (8-byte aligned) heavy list int2[BIN_HMAX].
+struct BinLds {
+  int32_t* acc;
+  int32_t* pos;
+  int32_t* roff;
+  int32_t* offp;
+  int32_t* lcnt;
+  int2* heavy;
+};
+
+__device__ __forceinline__ BinLds bin_lds(uint32_t* lds, int32_t nb) {
+  BinLds L;
+  L.acc = (int32_t*)lds;
+  L.pos = L.acc + BIN_TILE;
+  L.roff = L.pos + nb + 1;
+  L.offp = L.roff + nb;
+  L.lcnt = L.offp + nb;
+  const int32_t used = BIN_TILE + 4 * nb + 1;
+  L.heavy = (int2*)((int32_t*)lds + ((used + 1) & ~1));
+  return L;
+}
+
+size_t bin_lds_bytes(const SysDev& s) {
+  const int64_t used = BIN_TILE + 4LL * s.bnb + 1;
+  return (size_t)(4 * ((used + 1) & ~1LL) + 8 * BIN_HMAX);
+}
+
+// Sums into L.acc (zeroed by the caller, before the first barrier here) the
+// records that the tiles sent to tile `tile` in buffer rbuf.
+__device__ __forceinline__ void bin_receive(const SysDev& s, int32_t tile, int32_t rbuf,
+                                            const BinLds& L, int32_t* wsum) {
+  const int32_t nb = s.bnb;
+  const int tid = threadIdx.x;
+  const int32_t* cp = pick(s.bcnt[0], s.bcnt[1], rbuf) + (size_t)tile * nb;
+  const int32_t* op = s.boff + (size_t)tile * nb;
+  // counts of the regions addressed to this tile, two per thread (nb <= 2048)
+  const int32_t b0 = 2 * tid, b1 = 2 * tid + 1;
+  const int32_t c0 = b0 < nb ? cp[b0] : 0, c1 = b1 < nb ? cp[b1] : 0;
+  if (b0 < nb) L.roff[b0] = op[b0];
+  if (b1 < nb) L.roff[b1] = op[b1];
+  int32_t total;
+  const int32_t ex = block_exscan<BIN_NT>(c0 + c1, wsum, &total);
+  if (b0 < nb) L.pos[b0] = ex;
+  if (b1 < nb) L.pos[b1] = ex + c0;
+  if (tid == 0) L.pos[nb] = total;
+  __syncthreads();
+  const uint32_t* bp = pick(s.bins[0], s.bins[1], rbuf);
+  for (int32_t e0 = tid; e0 < total; e0 += 8 * BIN_NT) {
+    uint32_t rv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int32_t e = e0 + u * BIN_NT;
+      int32_t slot = 0;
+      if (e < total) {
+        // region: the last b with pos[b] <= e (empty regions are skipped)
+        int32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (L.pos[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        slot = L.roff[lo] + (e - L.pos[lo]);
+      }
+      rv[u] = bp[slot];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * BIN_NT < total)
+        atomicAdd(&L.acc[rv[u] & (BIN_TILE - 1)], (int32_t)(rv[u] >> BIN_TB));
+  }
+}
+
+// One record to the region (own tile -> tile of t).
+__device__ __forceinline__ void bin_put(const BinLds& L, uint32_t* bc, int32_t t, int32_t v) {
+  const int32_t tt = t >> BIN_TB;
+  const int32_t slot = atomicAdd(&L.lcnt[tt], 1);
+  bc[L.offp[tt] + slot] = (uint32_t)(t & (BIN_TILE - 1)) | ((uint32_t)v << BIN_TB);
+}
+
+// Entry jj of the row of neuron i in the layout's own order (Sy column i,
+// ELL column `rule` from row 1, CSR row i from e0): target and value, target
+// -1 past the end of the row.
+template <int LAYOUT>
+__device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t rule, int32_t v, int32_t e0,
+                                          int32_t jj) {
+  if (LAYOUT == L_OPT) return make_int2(s.sy[(int64_t)jj * s.q + i], v);
+  if (LAYOUT == L_ELL) return s.ell[(int64_t)(jj + 1) * s.m + rule];
+  return make_int2(s.out_col[e0 + jj], v);
+}
+
+// Entries j0, j0 + stride, ... below jend of one row; stops at the null entry.
+template <int LAYOUT>
+__device__ __forceinline__ void bin_walk(const SysDev& s, const BinLds& L, uint32_t* bc, int32_t i,
+                                         int32_t rule, int32_t v, int32_t e0, int32_t j0, int32_t stride,
+                                         int32_t jend) {
+  for (int32_t jj = j0; jj < jend; jj += stride) {
+    const int2 x = bin_entry<LAYOUT>(s, i, rule, v, e0, jj);
+    if (x.x < 0) break;
+    bin_put(L, bc, x.x, x.y);
+  }
+}
+
+// Row bound of a walk: the out-degree for CSR, the layout height for Sy and
+// ELL (their rows end at a null entry, or at the height).
+template <int LAYOUT>
+__device__ __forceinline__ int32_t bin_height(const SysDev& s, int32_t deg) {
+  return LAYOUT == L_CSR_PUSH ? deg : s.z;
+}
+
+template <int LAYOUT, int RB, uint32_t FLAGS>
+__device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t j, uint32_t* lds,
+                                         unsigned long long* red, int32_t* wsum, int32_t* hcount) {
+  constexpr bool DIG = (FLAGS & F_DIGEST) != 0;
+  constexpr bool CNT = (FLAGS & F_COUNTERS) != 0;
+  const BinLds L = bin_lds(lds, s.bnb);
+  int64_t k;
+  if (!step_prologue(s, tile, j, k)) return;
+  const int32_t nb = s.bnb;
+  const int32_t t0 = tile * BIN_TILE;
+  const int tid = threadIdx.x;
+
+  NeuronIn<RB> in[BIN_NPT];
+#pragma unroll
+  for (int r = 0; r < BIN_NPT; ++r) {
+    const int32_t t = t0 + tid + r * BIN_NT;
+    in[r].C = 0;
+    if (t < s.q) {
+      in[r].C = s.C[t];
+      prefetch_neuron<RB>(s, t, s.meta[t], in[r]);
+    } else {
+      in[r].meta = 0;
+    }
+    L.acc[tid + r * BIN_NT] = 0;
+  }
+  for (int32_t b = tid; b < nb; b += BIN_NT) {
+    L.offp[b] = s.boffp[(size_t)tile * nb + b];
+    L.lcnt[b] = 0;
+  }
+  if (tid == 0) *hcount = 0;
+  if (k > 0) bin_receive(s, tile, (int32_t)((k - 1) & 1), L, wsum);
+  __syncthreads();
+
+  Cnt cnt;
+  cnt.zero();
+  unsigned long long dig = 0;
+  bool anyact = false;
+  Sel o[BIN_NPT];
+#pragma unroll
+  for (int r = 0; r < BIN_NPT; ++r) {
+    o[r] = Sel{0, -1, false};
+    const int32_t lt = tid + r * BIN_NT;
+    const int32_t t = t0 + lt;
+    if (t >= s.q) continue;
+    int32_t C = in[r].C;
+    if (k > 0) {
+      const int32_t got = L.acc[lt];
+      if (in[r].meta & META_RECV) {
+        const uint32_t sum = (uint32_t)C + (uint32_t)got;
+        if ((int32_t)sum < 0) s.ctl->overflow = 1;
+        C = (int32_t)sum;
+        if (CNT) {
+          cnt.v[C_RECV] += 1;
+          cnt.v[C_INEDGES] += (unsigned long long)s.in_deg[t];
+        }
+      } else if (CNT) {
+        cnt.v[C_LOST] += (unsigned long long)got;
+      }
+    }
+    in[r].C = C;
+    if (DIG && k > 0)
+      dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
+    o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt);
+    anyact |= o[r].act;
+  }
+  const unsigned long long am = __ballot(anyact);
+  if (am && (tid & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;
+
+  // emission.  A thread walks the rows of its emitting neurons (at a fixed
+  // row, neighbouring threads read neighbouring columns of Sy / ELL):
+  // BIN_ROWS entries of each of its neurons are loaded together, then the
+  // rest of each row up to BIN_LIGHT entries in batches of BIN_ROWS.  Longer
+  // rows are finished below by the whole block.
+  uint32_t* bc = pick(s.bins[0], s.bins[1], k);
+  int32_t e0[BIN_NPT], jend[BIN_NPT], rule[BIN_NPT];
+#pragma unroll
+  for (int r = 0; r < BIN_NPT; ++r) {
+    const int32_t i = t0 + tid + r * BIN_NT;
+    rule[r] = o[r].erule;
+    e0[r] = 0;
+    jend[r] = 0;
+    if (o[r].emit > 0) {
+      int32_t deg = 0;
+      if (LAYOUT == L_CSR_PUSH) {
+        e0[r] = s.out_ptr[i];
+        deg = s.out_ptr[i + 1] - e0[r];
+      }
+      jend[r] = bin_height<LAYOUT>(s, deg);
+    }
+  }
+  bool more[BIN_NPT];
+  {
+    int2 x[BIN_NPT][BIN_ROWS];
+#pragma unroll
+    for (int r = 0; r < BIN_NPT; ++r)
+#pragma unroll
+      for (int u = 0; u < BIN_ROWS; ++u) {
+        const int32_t i = t0 + tid + r * BIN_NT;
+        // rows past the bound are clamped to the row's last entry and dropped
+        const int32_t jj = min(u, jend[r] - 1);
+        x[r][u] = jend[r] > 0 ? bin_entry<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], jj) : make_int2(-1, 0);
+        if (u >= jend[r]) x[r][u].x = -1;
+      }
+#pragma unroll
+    for (int r = 0; r < BIN_NPT; ++r) {
+      bool open = true;
+#pragma unroll
+      for (int u = 0; u < BIN_ROWS; ++u) {
+        open = open && x[r][u].x >= 0;
+        if (open) bin_put(L, bc, x[r][u].x, x[r][u].y);
+      }
+      more[r] = open && jend[r] > BIN_ROWS;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < BIN_NPT; ++r) {
+    if (!more[r]) continue;
+    const int32_t i = t0 + tid + r * BIN_NT;
+    const int32_t lim = min(jend[r], BIN_LIGHT);
+    bool open = true;
+    for (int32_t jb = BIN_ROWS; jb < lim && open; jb += BIN_ROWS) {
+      int2 x[BIN_ROWS];
+#pragma unroll
+      for (int u = 0; u < BIN_ROWS; ++u) {
+        x[u] = bin_entry<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], min(jb + u, lim - 1));
+        if (jb + u >= lim) x[u].x = -1;
+      }
+#pragma unroll
+      for (int u = 0; u < BIN_ROWS; ++u) {
+        open = open && x[u].x >= 0;
+        if (open) bin_put(L, bc, x[u].x, x[u].y);
+      }
+    }
+    // a row that filled BIN_LIGHT entries and goes on is heavy; its length
+    // comes from the CSR offsets, so the block reads no entry past it
+    if (open && jend[r] > BIN_LIGHT) {
+      const int32_t deg = s.out_ptr[i + 1] - s.out_ptr[i];
+      if (deg > BIN_LIGHT) {
+        const int32_t h = atomicAdd(hcount, 1);
+        // the entry keeps what the walk needs: the ELL column (rule slot) or
+        // the value sent along Sy / CSR
+        if (h < BIN_HMAX) L.heavy[h] = make_int2(i, LAYOUT == L_ELL ? rule[r] : o[r].emit);
+        else bin_walk<LAYOUT>(s, L, bc, i, rule[r], o[r].emit, e0[r], BIN_LIGHT, 1, deg);
+      }
+    }
+  }
+  if (CNT) {
+#pragma unroll
+    for (int r = 0; r < BIN_NPT; ++r) {
+      if (o[r].emit <= 0) continue;
+      const int32_t i = t0 + tid + r * BIN_NT;
+      const unsigned long long dg = (unsigned long long)(s.out_ptr[i + 1] - s.out_ptr[i]);
+      cnt.v[C_EDGES] += dg;
+      cnt.v[C_SENT] += dg * (unsigned long long)o[r].emit;
+    }
+  }
+  __syncthreads();
+  const int32_t nh = min(*hcount, BIN_HMAX);
+  for (int32_t h = 0; h < nh; ++h) {
+    const int2 hv = L.heavy[h];
+    const int32_t i = hv.x;
+    const int32_t ce0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - ce0;
+    bin_walk<LAYOUT>(s, L, bc, i, hv.y, hv.y, ce0, BIN_LIGHT + tid, BIN_NT, deg);
+  }
+  __syncthreads();
+  for (int32_t b = tid; b < nb; b += BIN_NT)
+    pick(s.bcnt[0], s.bcnt[1], k)[(size_t)b * nb + tile] = L.lcnt[b];
+
+  if (DIG && k > 0) block_add64<BIN_NT>(dig, (unsigned long long*)&s.digests[(k - 1) % s.ring], red);
+  if (CNT) {
+    unsigned long long* cs = s.counters + (k % s.ring) * NCOUNT;
+    unsigned long long* cq = s.counters + (((k - 1) % s.ring + s.ring) % s.ring) * NCOUNT;
+    for (int x = 0; x < NCOUNT; ++x) {
+      const bool recv_side = (x == C_LOST || x == C_RECV || x == C_INEDGES);
+      if (recv_side && k == 0) continue;
+      block_add64<BIN_NT>(cnt.v[x], recv_side ? &cq[x] : &cs[x], red);
+    }
+  }
+}
+
+}  // namespace snp
+
+namespace snp {
+
+template <int LAYOUT, int RB, uint32_t FLAGS>
+__global__ void __launch_bounds__(BIN_NT) step_bin_kernel(SysDev s, int32_t j) {
+  extern __shared__ uint4 lds4[];
+  __shared__ unsigned long long red[BIN_NT / 64];
+  __shared__ int32_t wsum[BIN_NT / 64 + 1];
+  __shared__ int32_t hcount;
+  bin_body<LAYOUT, RB, FLAGS>(s, blockIdx.x, j, (uint32_t*)lds4, red, wsum, &hcount);
+}
+
+// Batched form: block b runs tile tiles[b].y of system members[tiles[b].x].
+template <int LAYOUT, int RB, uint32_t FLAGS>
+__global__ void __launch_bounds__(BIN_NT)
+    step_bin_batch_kernel(const SysDev* __restrict__ members, const int2* __restrict__ tiles,
+                          const int32_t* __restrict__ ntiles, int32_t j) {
+  extern __shared__ uint4 lds4[];
+  __shared__ unsigned long long red[BIN_NT / 64];
+  __shared__ int32_t wsum[BIN_NT / 64 + 1];
+  __shared__ int32_t hcount;
+  if ((int32_t)blockIdx.x >= *ntiles) return;
+  const int2 tm = tiles[blockIdx.x];
+  const SysDev s = members[tm.x];
+  bin_body<LAYOUT, RB, FLAGS>(s, tm.y, j, (uint32_t*)lds4, red, wsum, &hcount);
+}
+
+// Per-target sums of the records in buffer rbuf (reads of a state whose
+// reception is still pending).
+__global__ void __launch_bounds__(BIN_NT) bin_gather_kernel(SysDev s, int32_t rbuf, int32_t* out) {
+  extern __shared__ uint4 lds4[];
+  __shared__ int32_t wsum[BIN_NT / 64 + 1];
+  const BinLds L = bin_lds((uint32_t*)lds4, s.bnb);
+  const int32_t t0 = blockIdx.x * BIN_TILE;
+  for (int r = 0; r < BIN_NPT; ++r) L.acc[threadIdx.x + r * BIN_NT] = 0;
+  bin_receive(s, blockIdx.x, rbuf, L, wsum);
+  __syncthreads();
+  for (int r = 0; r < BIN_NPT; ++r) {
+    const int32_t t = t0 + threadIdx.x + r * BIN_NT;
+    if (t < s.q) out[t] = L.acc[threadIdx.x + r * BIN_NT];
+  }
+}
+
+hipError_t launch_bin_gather(const SysDev& s, int32_t rbuf, int32_t* out, hipStream_t st) {
+  bin_gather_kernel<<<s.bnb, BIN_NT, bin_lds_bytes(s), st>>>(s, rbuf, out);
+  return hipGetLastError();
+}
+
+template <int RB, uint32_t FL>
+static hipError_t launch_bin_rf(const SysDev& s, int32_t j, hipStream_t st) {
+  const dim3 grid(s.bnb);
+  const size_t lds = bin_lds_bytes(s);
+  switch (s.layout) {
+    case L_OPT: step_bin_kernel<L_OPT, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
+    case L_ELL: step_bin_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
+    case L_CSR_PUSH: step_bin_kernel<L_CSR_PUSH, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int RB, uint32_t FL>
+static hipError_t launch_bin_batch_rf(const SysDev& s, const SysDev* members, const int2* tiles,
+                                      const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                                      hipStream_t st) {
+  switch (s.layout) {
+    case L_OPT:
+      step_bin_batch_kernel<L_OPT, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
+      break;
+    case L_ELL:
+      step_bin_batch_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
+      break;
+    case L_CSR_PUSH:
+      step_bin_batch_kernel<L_CSR_PUSH, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define SNP_FLAGS_DISPATCH(FN, RB, ...)                                \
+  switch (s.flags & (F_DIGEST | F_COUNTERS)) {                         \
+    case 0: return FN<RB, 0u>(__VA_ARGS__);                            \
+    case F_DIGEST: return FN<RB, F_DIGEST>(__VA_ARGS__);               \
+    case F_COUNTERS: return FN<RB, F_COUNTERS>(__VA_ARGS__);           \
+    default: return FN<RB, F_DIGEST | F_COUNTERS>(__VA_ARGS__);        \
+  }
+
+hipError_t launch_step_bin(const SysDev& s, int32_t j, hipStream_t st) {
+  if (s.bnb > BIN_MAX_TILES) return hipErrorInvalidValue;
+  if (s.rule_bytes == 8) {
+    SNP_FLAGS_DISPATCH(launch_bin_rf, 8, s, j, st)
+  }
+  SNP_FLAGS_DISPATCH(launch_bin_rf, 16, s, j, st)
+}
+
+hipError_t launch_step_bin_batch(const SysDev& s, const SysDev* members, const int2* tiles,
+                                 const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
+                                 hipStream_t st) {
+  if (s.rule_bytes == 8) {
+    SNP_FLAGS_DISPATCH(launch_bin_batch_rf, 8, s, members, tiles, ntiles, grid, lds, j, st)
+  }
+  SNP_FLAGS_DISPATCH(launch_bin_batch_rf, 16, s, members, tiles, ntiles, grid, lds, j, st)
+}
+
+#undef SNP_FLAGS_DISPATCH
+
+}  // namespace snp

@@ -54,14 +54,17 @@ def test_footprint_orders():
     dict(rules=[(0, -1, 0, 1, 1, 0)]),
     dict(rules=[(0, 1, 0, 1, 1, -1)]),
     dict(rules=[(2, 1, 0, 1, 1, 0)]),
+    dict(pull_mode=3),
+    dict(pull_mode=-1),
 ])
 def test_invalid_systems_rejected_before_any_device_call(bad):
     from paper_2408_04343_amd import binding
-    kw = dict(q=2, s0=[1, 1], rules=[(0, 1, 0, 1, 1, 0)], src=[0], dst=[1])
+    kw = dict(q=2, s0=[1, 1], rules=[(0, 1, 0, 1, 1, 0)], src=[0], dst=[1], pull_mode=0)
     kw.update(bad)
     s0 = kw["s0"] if kw["q"] == 2 else []
     with pytest.raises(binding.SnpError) as ei:
-        binding.System(kw["q"], s0, kw["rules"], kw["src"], kw["dst"], memory="hip", stream=0)
+        binding.System(kw["q"], s0, kw["rules"], kw["src"], kw["dst"], memory="hip", stream=0,
+                       pull_mode=kw["pull_mode"])
     assert ei.value.status == -1
 
 
@@ -90,3 +93,34 @@ def test_rules_array_layout_matches_header():
     o = binding.Opts()
     binding.lib.snp_opts_default(ct.byref(o))
     assert (o.layout, o.select, o.semantics, o.chunk, o.device) == (0, 0, 0, 64, -1)
+    assert o.pull_mode == 0
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """sizeof / offsetof of every ABI struct as a C compiler lays out
+    include/snp.h equal the ctypes mirrors of the binding."""
+    import ctypes as ct
+    import shutil
+    import subprocess
+    from paper_2408_04343_amd import binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"snp_opts": binding.Opts, "snp_rule": binding.Rule, "snp_counters": binding.Counters,
+               "snp_info_t": binding.Info, "snp_batch_opts": binding.BatchOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "snp.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _t in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ct.sizeof(py), cname
+        for f, _t in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -12,7 +12,21 @@ from paper_2408_04343_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["csr_pull", "optimized", "ell", "csr_push"]
+# "csr_pull_gather" is the pull layout with its reception forced to read
+# emitted values from device memory (plain "csr_pull" stages them in LDS at
+# these sizes); the push layouts run binned at these sizes, "*_atomic" forces
+# device-wide atomic adds
+LAYOUTS = ["csr_pull", "csr_pull_gather", "optimized", "ell", "csr_push",
+           "optimized_atomic", "ell_atomic", "csr_push_atomic"]
+
+
+def lk(layout):
+    """System keyword arguments of a test layout name."""
+    if layout == "csr_pull_gather":
+        return {"layout": "csr_pull", "pull_mode": "gather"}
+    if layout.endswith("_atomic"):
+        return {"layout": layout[:-len("_atomic")], "push_mode": "atomic"}
+    return {"layout": layout}
 SEMS = [("standard", orc.SEM_STANDARD), ("paper_kernel", orc.SEM_PAPER_KERNEL)]
 
 
@@ -31,7 +45,7 @@ def oracle_of(spec, sem, sel=None, seed=None):
 
 
 def gpu_of(binding, spec, layout, sem_name, **kw):
-    return binding.System.from_spec(spec, layout=layout, semantics=sem_name, **kw)
+    return binding.System.from_spec(spec, semantics=sem_name, **lk(layout), **kw)
 
 
 def compare_every_step(binding, spec, layout, sem_name, sem, steps, **kw):
@@ -83,7 +97,7 @@ def test_hand_trace_h1(binding, layout):
 @pytest.mark.parametrize("sel,seed", [("first", 0), ("hash", 1)])
 def test_hand_trace_h2(binding, layout, sel, seed):
     rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
-    g = binding.System(1, [4], rules, [], [], layout=layout, select=sel, seed=seed)
+    g = binding.System(1, [4], rules, [], [], select=sel, seed=seed, **lk(layout))
     g.step(10)
     assert g.steps_done() == (2, True)
     assert g.read_config().tolist() == [0]
@@ -96,7 +110,7 @@ def test_sort_family_closed_form(binding, layout):
     for n in (3, 17, 100):
         v = rng.integers(1, 60, size=n).tolist() if n != 100 else list(range(100, 0, -1))
         spec = wl.sort_system(v)
-        g = binding.System.from_spec(spec, layout=layout)
+        g = binding.System.from_spec(spec, **lk(layout))
         g.step(10_000)
         steps, halted = g.steps_done()
         assert (steps, halted) == (max(v) + 1, True)
@@ -134,7 +148,7 @@ def test_graph_chunks_digests(binding, layout):
     spec = wl.small_random(21, 9000, max_deg=16, max_rules=4, dmax=3, c0max=8,
                            select=wl.SELECT_HASH)
     ref = oracle_of(spec, orc.SEM_STANDARD).step_record(300, want_state=False)
-    g = binding.System.from_spec(spec, layout=layout, digest=True, chunk=64)
+    g = binding.System.from_spec(spec, **lk(layout), digest=True, chunk=64)
     g.step(130)       # two captured chunks + direct launches
     g.step(170)
     n = ref["steps"]
@@ -147,7 +161,7 @@ def test_counters_match_oracle(binding, layout):
     spec = wl.small_random(8, 5000, max_deg=10, max_rules=4, dmax=3, c0max=8)
     for sem_name, sem in SEMS:
         ref = oracle_of(spec, sem).step_record(40, want_state=False)
-        g = binding.System.from_spec(spec, layout=layout, semantics=sem_name, counters=True)
+        g = binding.System.from_spec(spec, **lk(layout), semantics=sem_name, counters=True)
         g.step(40)
         got = g.read_counters(0, ref["steps"])
         assert got == ref["counters"], (layout, sem_name)
@@ -156,14 +170,14 @@ def test_counters_match_oracle(binding, layout):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_split_and_resume_equal_uninterrupted(binding, layout):
     spec = wl.small_random(31, 4000, max_deg=8, max_rules=3, dmax=3, select=wl.SELECT_HASH)
-    a = binding.System.from_spec(spec, layout=layout)
+    a = binding.System.from_spec(spec, **lk(layout))
     a.step(37)
     a.step(1)
     a.step(62)
-    b = binding.System.from_spec(spec, layout=layout)
+    b = binding.System.from_spec(spec, **lk(layout))
     b.step(40)
     snap = (b.read_config(), b.read_delays(), b.read_pending(), b.read_spiking())
-    c = binding.System.from_spec(spec, layout=layout)
+    c = binding.System.from_spec(spec, **lk(layout))
     c.write_state(*snap, k=40)
     c.step(60)
     ref = oracle_of(spec, orc.SEM_STANDARD)
@@ -203,16 +217,84 @@ def test_pull_several_lds_chunks(binding):
     spec = wl.config2(q=600_000, steps=20)
     ref = oracle_of(spec, orc.SEM_STANDARD).step_record(20, want_state=False)
     for layout in ("csr_pull", "csr_push"):
-        g = binding.System.from_spec(spec, layout=layout, digest=True)
+        g = binding.System.from_spec(spec, **lk(layout), digest=True)
         g.step(20)
         assert np.array_equal(g.read_digests(0, 20), ref["digests"]), layout
         g.close()
 
 
+def test_pull_gather_several_chunks(binding):
+    # gather tiles are 1024 neurons, so a chunk holds 2^22 - 128 sources and
+    # 4.2M neurons span two
+    spec = wl.small_random(11, 4_200_000, max_deg=4, max_rules=3, dmax=2, c0max=6,
+                           select=wl.SELECT_HASH)
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(12, want_state=False)
+    g = binding.System.from_spec(spec, layout="csr_pull", pull_mode="gather", digest=True)
+    assert g.info()["pull_chunks"] == 2 and g.info()["pull_mode"] == binding.PULL_GATHER
+    g.step(12)
+    assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"])
+
+
+def test_pull_auto_mode_choice(binding):
+    # dense in-edges per block: staged; a large sparse system: gather
+    g = binding.System.from_spec(wl.config1(), layout="csr_pull")
+    assert g.info()["pull_mode"] == binding.PULL_STAGED
+    sparse = wl.small_random(5, 300_000, max_deg=2, max_rules=2, dmax=2, c0max=4)
+    h = binding.System.from_spec(sparse, layout="csr_pull")
+    assert h.info()["pull_mode"] == binding.PULL_GATHER
+    ref = oracle_of(sparse, orc.SEM_STANDARD).step_record(10, want_state=False)
+    h2 = binding.System.from_spec(sparse, layout="csr_pull", digest=True)
+    h2.step(10)
+    assert np.array_equal(h2.read_digests(0, ref["steps"]), ref["digests"])
+
+
+def _heavy_spec(n_heavy, hub_deg, q=6000, seed=21):
+    """Neurons 0..n_heavy-1 fire every step (a+/a -> a) along 65..128
+    synapses, two hubs along hub_deg; the rest forget."""
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(q, np.int64)
+    deg[:n_heavy] = rng.integers(65, 129, size=n_heavy)
+    deg[n_heavy:n_heavy + 2] = hub_deg
+    deg[n_heavy + 2:] = rng.integers(0, 4, size=q - n_heavy - 2)
+    src, dst = wl.distinct_targets(rng, q, deg)
+    rules = []
+    for i in range(q):
+        if i < n_heavy + 2:
+            rules.append((i, 1, 1, 1, 1, int(rng.integers(0, 2))))
+        else:
+            rules.append((i, 2, 1, 2, 1, 0))
+            rules.append((i, 1, 0, 1, 0, 0))
+    spikes0 = rng.integers(1, 5, size=q).astype(np.int32)
+    return wl.SnpSpec("heavy%d" % n_heavy, q, spikes0, np.array(rules, np.int32), src, dst,
+                      wl.SELECT_HASH, 5, 12)
+
+
+@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push"])
+@pytest.mark.parametrize("n_heavy", [40, 1100])
+def test_binned_heavy_rows(binding, layout, n_heavy):
+    # rows longer than a thread walks alone go to the block; more heavy
+    # neurons than the block's list holds are walked by their threads
+    spec = _heavy_spec(n_heavy, 2500)
+    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 12, push_mode="binned")
+
+
+def test_push_auto_mode_choice(binding):
+    g = binding.System.from_spec(wl.config1(), layout="ell")
+    assert g.info()["push_mode"] == binding.PUSH_BINNED
+    q = 2048 * 4096 + 1   # one tile more than the binned form takes
+    big = binding.System(q, np.zeros(q, np.int32), np.zeros((0, 6), np.int32), [], [], layout="csr_push")
+    assert big.info()["push_mode"] == binding.PUSH_ATOMIC
+    big.close()
+    with pytest.raises(binding.SnpError) as ei:
+        binding.System(q, np.zeros(q, np.int32), np.zeros((0, 6), np.int32), [], [], layout="csr_push",
+                       push_mode="binned")
+    assert ei.value.status == -6
+
+
 def test_overflow_reported(binding):
     big = 2 ** 31 - 2
     for layout in LAYOUTS:
-        g = binding.System(2, [1, big], [(0, 1, 0, 1, 5, 0)], [0], [1], layout=layout)
+        g = binding.System(2, [1, big], [(0, 1, 0, 1, 5, 0)], [0], [1], **lk(layout))
         g.step(1)
         with pytest.raises(binding.SnpError) as ei:
             g.steps_done()
@@ -255,12 +337,13 @@ def _batch_specs(n, seed=0, qmax=9000):
                             dmax=3, c0max=8, select=wl.SELECT_HASH) for j, q in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("layout", ["csr_pull", "csr_push", "optimized"])
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_push", "optimized", "ell",
+                                    "csr_push_atomic"])
 def test_batch_equals_alone(binding, layout):
     specs = _batch_specs(14, seed=1)
     steps = 150
     refs = [oracle_of(sp, orc.SEM_STANDARD).step_record(steps, want_state=False) for sp in specs]
-    members = [binding.System.from_spec(sp, layout=layout, digest=True, emit_bits=2)
+    members = [binding.System.from_spec(sp, **lk(layout), digest=True, emit_bits=2)
                for sp in specs]
     b = binding.Batch(members, chunk=32)
     b.step(steps)      # 4 graph chunks + direct launches
@@ -308,6 +391,32 @@ def test_batch_step_limits_and_membership(binding):
     b.close()
 
 
+@pytest.mark.parametrize("layout,modes", [("csr_pull", ("staged", "gather")),
+                                          ("ell", ("atomic", "binned")),
+                                          ("csr_push", ("binned", "atomic"))])
+def test_batch_mixes_reception_modes(binding, layout, modes):
+    # members alternate between the two reception modes: two launches per
+    # step, each member's digests equal its run alone
+    specs = _batch_specs(9, seed=4)
+    steps = 100
+    refs = [oracle_of(sp, orc.SEM_STANDARD).step_record(steps, want_state=False) for sp in specs]
+    key = "pull_mode" if layout == "csr_pull" else "push_mode"
+    members = [binding.System.from_spec(sp, layout=layout, digest=True, emit_bits=2,
+                                        **{key: modes[j % 2]}) for j, sp in enumerate(specs)]
+    for g in members:
+        g.set_step_limit(steps)
+    b = binding.Batch(members[:4], chunk=32)
+    b.step(40)
+    for g in members[4:]:
+        b.add(g)       # joins at step 0 of its own while the others are at 40
+    b.step(steps)      # graph chunks and direct launches, both groups
+    b.sync()
+    for sp, g, ref in zip(specs, members, refs):
+        assert g.steps_done()[0] == ref["steps"], sp.name
+        assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"]), sp.name
+    b.close()
+
+
 def test_batch_rejects_mixed_members(binding):
     a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", emit_bits=2)
     c = binding.System.from_spec(wl.small_random(2, 100), layout="csr_push")
@@ -340,11 +449,11 @@ def test_config2_full_size_digests(binding):
     assert np.array_equal(g.read_spiking(), r["S"])
 
 
-@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push"])
+@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push", "csr_push_atomic"])
 def test_config2_full_size_push_layouts(binding, layout):
     spec = wl.config2(steps=40)
     ref = oracle_of(spec, orc.SEM_STANDARD).step_record(40, want_state=False)
-    g = binding.System.from_spec(spec, layout=layout, digest=True)
+    g = binding.System.from_spec(spec, **lk(layout), digest=True)
     g.step(40)
     assert np.array_equal(g.read_digests(0, 40), ref["digests"])
 
