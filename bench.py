@@ -45,7 +45,7 @@ def layout_bytes(layout, q, c, emit_w):
         # in-list offsets, in-lists of receiving neurons, emitted values written + read once
         return 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
     push = 8 * q + 4 * G          # receive buffer read + cleared, one 4-byte update per delivery
-    if layout == "optimized":
+    if layout in ("optimized", "sliced"):
         return push + 4 * (G + E)     # Sy entries of emitters (+ terminator)
     if layout == "ell":
         return push + 8 * (G + E)     # (neuron, value) pairs of emitting rules (+ terminator)
@@ -207,7 +207,7 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     return out
 
 
-def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optimized", "csr_push")):
+def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optimized", "sliced", "csr_push")):
     """Config 3: 4,194,304 neurons, power-law out-degree (exponent 2.1, 1..4,096),
     in-degree hubs, hash choice, 500 steps.  ELL is reported analytically (its
     padded matrix, (z+1) x m pairs, exceeds the device memory)."""
@@ -216,12 +216,21 @@ def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optim
     spec = wl.config3(steps=steps)
     gen_s = time.time() - t0
     z = spec.max_outdeg()
+    deg = np.bincount(spec.src, minlength=spec.q)
+    pad = np.zeros(((spec.q + 63) // 64) * 64, np.int64)
+    pad[:spec.q] = deg
+    sliced_slots = int(pad.reshape(-1, 64).max(axis=1).sum()) * 64
     out = {"workload": "config3-skewed: 4,194,304 neurons, power-law out-degree (2.1, max %d), "
                        "in-degree hubs, 1-4 rules, delays 0..5, hash choice" % z,
            "q": spec.q, "rules": spec.m, "synapses": spec.nnz, "max_out_degree": z,
            "gen_s": round(gen_s, 1),
            "ell_bytes_analytic": 8 * (z + 1) * spec.m,
-           "optimized_bytes_analytic": 4 * z * spec.q, "layouts": {}}
+           "optimized_bytes_analytic": 4 * z * spec.q,
+           "sliced_bytes_analytic": 4 * sliced_slots,
+           "padding_slots_per_synapse": {"ell": round((z + 1) * spec.m / spec.nnz, 1),
+                                         "optimized": round(z * spec.q / spec.nnz, 1),
+                                         "sliced": round(sliced_slots / spec.nnz, 1), "csr": 1.0},
+           "layouts": {}}
     for lay in layouts:
         try:
             r = run_layout(binding, torch, spec, lay, steps, warmup, 64)
@@ -280,6 +289,48 @@ def measured_traffic():
     return t.get("traffic_bytes_per_launch"), t
 
 
+def _pmc_per_kernel(csv_path, counter):
+    """Per-dispatch values of `counter` (KiB) by kernel name, in dispatch order."""
+    import csv
+    out = {}
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] == counter:
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def write_traffic(run_dir, copy_dir, kernel, out_path, skip=8):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of this
+    bench (FETCH_SIZE in run_dir/fetch, WRITE_SIZE in run_dir/write) and of
+    the copy probe of 512 MiB (same layout under copy_dir), each counter scaled by what
+    it reads for the plain copy of known size.  The first `skip` launches
+    (start-up steps) are left out."""
+    f = _pmc_per_kernel(os.path.join(run_dir, "fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    w = _pmc_per_kernel(os.path.join(run_dir, "write", "run_counter_collection.csv"), "WRITE_SIZE")
+    cf = _pmc_per_kernel(os.path.join(copy_dir, "fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    cw = _pmc_per_kernel(os.path.join(copy_dir, "write", "run_counter_collection.csv"), "WRITE_SIZE")
+    kf = [v for k, v in f.items() if kernel in k]
+    kw = [v for k, v in w.items() if kernel in k]
+    copy_f = [v for k, v in cf.items() if "copyBuffer" in k][0]
+    copy_w = [v for k, v in cw.items() if "copyBuffer" in k][0]
+    copy_bytes = 512 * (1 << 20)
+    fetch_scale = copy_bytes / (float(np.median(copy_f)) * 1024)
+    write_scale = copy_bytes / (float(np.median(copy_w)) * 1024)
+    fk = np.array(kf[0][skip:]) * 1024 * fetch_scale
+    wk = np.array(kw[0][skip:]) * 1024 * write_scale
+    t = {"kernel": kernel, "source_hash": kernel_source_hash(),
+         "launches": int(fk.size), "fetch_kib_raw_mean": float(np.mean(kf[0][skip:])),
+         "write_kib_raw_mean": float(np.mean(kw[0][skip:])),
+         "copy_fetch_kib_raw": float(np.median(copy_f)), "copy_write_kib_raw": float(np.median(copy_w)),
+         "fetch_scale": fetch_scale, "write_scale": write_scale,
+         "read_bytes_per_launch": float(np.mean(fk)), "write_bytes_per_launch": float(np.mean(wk)),
+         "traffic_bytes_per_launch": float(np.mean(fk) + np.mean(wk))}
+    with open(out_path, "w") as fh:
+        json.dump(t, fh, indent=1)
+    print(json.dumps(t))
+
+
 def copy_probe(mib):
     """A plain device copy of known size (calibrates the memory counters)."""
     import torch
@@ -301,7 +352,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--layout", default="csr_pull")
-    ap.add_argument("--layouts", default="csr_pull,optimized,ell,csr_push")
+    ap.add_argument("--layouts", default="csr_pull,optimized,sliced,ell,csr_push")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-counters", action="store_true")
@@ -313,7 +364,12 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    ap.add_argument("--write-traffic", nargs=4, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "OUT"),
+                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the traffic file")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
         return

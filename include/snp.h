@@ -58,6 +58,10 @@ extern "C" {
 #define SNP_LAYOUT_ELL       2
 #define SNP_LAYOUT_CSR_PUSH  3
 #define SNP_LAYOUT_CSR_PULL  4
+/* Optimized layout cut into slices of 64 consecutive neurons, each slice as
+ * tall as its own largest out-degree (Sec. 4 pads every column to the global
+ * MaxOutDegree, which a few hub neurons make enormous).                     */
+#define SNP_LAYOUT_SLICED    5
 
 /* Choice among the applicable rules of an open neuron (Sec. 5.2 replaces
  * SAMPLE_ONE by the first applicable rule):
@@ -236,6 +240,7 @@ int snp_write_state(snp_sys* sys, const int32_t* config, const int32_t* delays,
 
 /* Device copy of the representation, for inspection (host buffers):
  *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
+ *   which = SNP_LAYOUT_SLICED: the slices expanded to the same [z][q] Sy;
  *   which = SNP_LAYOUT_ELL: M^s as [z'][m][2] int32 (neuron, value), columns
  *           in caller rule id order;
  *   which = SNP_LAYOUT_CSR_PUSH: out-neighbour row starts [q+1] then targets.

@@ -16,13 +16,13 @@ import numpy as np
 
 from . import build as _build
 
-LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL = 0, 1, 2, 3, 4
+LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL, LAYOUT_SLICED = 0, 1, 2, 3, 4, 5
 SELECT_FIRST, SELECT_HASH = 0, 1
 SEM_STANDARD, SEM_PAPER_KERNEL = 0, 1
 F_DIGEST, F_COUNTERS, F_NO_GRAPH, F_WIDE_RULES = 0x1, 0x2, 0x4, 0x8
 
 LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL,
-           "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL}
+           "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL, "sliced": LAYOUT_SLICED}
 SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
 SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
 PULL_AUTO, PULL_STAGED, PULL_GATHER = 0, 1, 2

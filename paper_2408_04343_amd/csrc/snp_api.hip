@@ -132,6 +132,11 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
     }
     p.add(4LL * std::max<int64_t>(nnz, 1));
     if (layout == L_OPT) p.add(4LL * z * q);
+    if (layout == L_SLICED) {  // at most the global height, at most 64 slots per synapse
+      const int64_t ns = (q + SLICE - 1) / SLICE;
+      p.add(8 * (ns + 1));
+      p.add(4 * std::min<int64_t>((int64_t)z * ns * SLICE, (int64_t)SLICE * nnz));
+    }
     if (layout == L_ELL) p.add(8LL * (z + 1) * std::max(m, 1));
   }
   return p.bytes;
@@ -346,7 +351,7 @@ int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layo
                   int64_t ring, int64_t* bytes) {
   if (q < 1 || m < 0 || nsyn < 0 || zmax < 0 || !bytes) return fail(SNP_EINVAL, "bad shape");
   if (layout == SNP_LAYOUT_AUTO) layout = SNP_LAYOUT_CSR_PULL;
-  if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
+  if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_SLICED) return fail(SNP_EINVAL, "bad layout");
   *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16, -1);
   return SNP_OK;
 }
@@ -364,7 +369,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   if (!spikes0 || (m > 0 && !rules) || (nsyn > 0 && (!syn_src || !syn_dst)))
     return fail(SNP_EINVAL, "null array");
   if (o.layout == SNP_LAYOUT_AUTO) o.layout = SNP_LAYOUT_CSR_PULL;
-  if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_CSR_PULL) return fail(SNP_EINVAL, "bad layout");
+  if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_SLICED) return fail(SNP_EINVAL, "bad layout");
   if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
   if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_GATHER) return fail(SNP_EINVAL, "bad pull_mode");
   if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_BINNED) return fail(SNP_EINVAL, "bad push_mode");
@@ -657,7 +662,24 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.out_ptr = p;
     if ((st = upload(s, &p, oc.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
     d.out_col = p;
-    if (o.layout == SNP_LAYOUT_OPTIMIZED) {
+    if (o.layout == SNP_LAYOUT_SLICED) {
+      const int64_t ns = ((int64_t)q + SLICE - 1) / SLICE;
+      std::vector<int64_t> off((size_t)ns + 1, 0);
+      for (int64_t b = 0; b < ns; ++b) {
+        int32_t h = 0;
+        for (int64_t i = b * SLICE; i < std::min<int64_t>(q, (b + 1) * SLICE); ++i)
+          h = std::max(h, op[(size_t)i + 1] - op[(size_t)i]);
+        off[(size_t)b + 1] = off[(size_t)b] + (int64_t)h * SLICE;
+      }
+      int64_t* po;
+      if ((st = upload(s, &po, off.data(), off.size())) != SNP_OK) return bail(st);
+      d.sy_off = po;
+      int32_t* sy = nullptr;
+      if ((st = alloc_fill(s, (void**)&sy, 4 * (size_t)std::max<int64_t>(off.back(), 1), 0xFF)) != SNP_OK)
+        return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "sliced Sy does not fit in device memory") : st);
+      d.sy = sy;
+      if (hipSuccess != launch_build_sy_sliced(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy_sliced"));
+    } else if (o.layout == SNP_LAYOUT_OPTIMIZED) {
       int32_t* sy = (int32_t*)s->dalloc(4 * (size_t)z * q);
       if (!sy) return bail(fail(SNP_ENOMEM, "Sy does not fit in device memory"));
       d.sy = sy;
@@ -911,7 +933,7 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
   DevScope ds(s->dev);
   const int32_t q = s->q, m = s->m, z = s->z;
   int64_t need = 0;
-  if (which == SNP_LAYOUT_OPTIMIZED) need = (int64_t)z * q;
+  if (which == SNP_LAYOUT_OPTIMIZED || which == SNP_LAYOUT_SLICED) need = (int64_t)z * q;
   else if (which == SNP_LAYOUT_ELL) need = 2LL * (z + 1) * m;
   else if (which == SNP_LAYOUT_CSR_PUSH) need = (int64_t)q + 1 + s->nnz;
   else if (which == SNP_LAYOUT_CSR_PULL) need = (int64_t)q + 1 + s->nnz;
@@ -921,8 +943,20 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
   if (count < need) return fail(SNP_EINVAL, "buffer too small");
   HIPCHK(hipStreamSynchronize(s->stream));
   if (which == SNP_LAYOUT_OPTIMIZED) {
-    if (!s->d.sy) return fail(SNP_EINVAL, "handle does not use the Optimized layout");
+    if (!s->d.sy || s->d.layout != L_OPT) return fail(SNP_EINVAL, "handle does not use the Optimized layout");
     HIPCHK(hipMemcpy(out, s->d.sy, 4 * (size_t)need, hipMemcpyDeviceToHost));
+  } else if (which == SNP_LAYOUT_SLICED) {
+    if (!s->d.sy || s->d.layout != L_SLICED) return fail(SNP_EINVAL, "handle does not use the sliced layout");
+    const int64_t ns = ((int64_t)q + SLICE - 1) / SLICE;
+    std::vector<int64_t> off((size_t)ns + 1);
+    HIPCHK(hipMemcpy(off.data(), s->d.sy_off, 8 * off.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> tmp((size_t)std::max<int64_t>(off.back(), 1));
+    HIPCHK(hipMemcpy(tmp.data(), s->d.sy, 4 * (size_t)off.back(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < q; ++i) {
+      const int64_t b = i / SLICE, h = (off[(size_t)b + 1] - off[(size_t)b]) / SLICE;
+      for (int64_t r = 0; r < z; ++r)
+        out[r * q + i] = r < h ? tmp[(size_t)(off[(size_t)b] + r * SLICE + i % SLICE)] : -1;
+    }
   } else if (which == SNP_LAYOUT_ELL) {
     if (!s->d.ell) return fail(SNP_EINVAL, "handle does not use the ELL layout");
     std::vector<int32_t> tmp((size_t)need);

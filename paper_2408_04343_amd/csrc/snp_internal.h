@@ -6,7 +6,8 @@
 
 namespace snp {
 
-enum : int32_t { L_OPT = 1, L_ELL = 2, L_CSR_PUSH = 3, L_CSR_PULL = 4 };
+enum : int32_t { L_OPT = 1, L_ELL = 2, L_CSR_PUSH = 3, L_CSR_PULL = 4, L_SLICED = 5 };
+constexpr int32_t SLICE = 64;           // neurons per slice of the sliced Optimized layout
 enum : int32_t { SEL_FIRST = 0, SEL_HASH = 1 };
 enum : int32_t { SEM_STANDARD = 0, SEM_PAPER = 1 };
 enum : uint32_t { F_DIGEST = 1u, F_COUNTERS = 2u };
@@ -72,7 +73,9 @@ struct SysDev {
   const int32_t* rid;        // [m] caller id of each slot
   // push representations
   int32_t* delta[2];         // spikes received at step k, by k & 1
-  const int32_t* sy;         // OPTIMIZED: [z][q] row-major, -1 = null
+  const int32_t* sy;         // OPTIMIZED: [z][q] row-major, -1 = null; SLICED: the slices
+  const int64_t* sy_off;     // SLICED: [q/64 + 1] first entry of each slice; slice b is
+                             //   [h_b][64] row-major, h_b = (sy_off[b+1] - sy_off[b]) / 64
   const int2* ell;           // ELL: [z+1][m] row-major (neuron, value), (-1, 0) = null
   const int32_t* out_ptr;    // CSR_PUSH: [q+1]
   const int32_t* out_col;    // CSR_PUSH: [nnz]
@@ -142,6 +145,7 @@ hipError_t launch_materialize(const SysDev& s, int32_t rbuf, int32_t sbuf, int32
 hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, int32_t q,
                          unsigned long long* out, hipStream_t st);
 hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st);
+hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st);
 hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st);
 hipError_t launch_restore(const SysDev& s, int32_t sbuf, const int32_t* C, const int32_t* D,
                           const int32_t* P, const int32_t* S, const int32_t* slot_of_rule,

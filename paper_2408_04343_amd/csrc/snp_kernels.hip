@@ -240,6 +240,21 @@ hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Sliced Sy: neuron i is column i % 64 of slice i / 64, rows up to the
+// slice's height, -1 padding.
+__global__ void build_sy_sliced_kernel(SysDev s, int32_t* sy) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.q) return;
+  const int64_t b0 = s.sy_off[i / SLICE], h = (s.sy_off[i / SLICE + 1] - b0) / SLICE;
+  const int32_t e0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - e0;
+  for (int64_t r = 0; r < h; ++r) sy[b0 + r * SLICE + i % SLICE] = r < deg ? s.out_col[e0 + r] : -1;
+}
+
+hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st) {
+  build_sy_sliced_kernel<<<(s.q + 255) / 256, 256, 0, st>>>(s, sy);
+  return hipGetLastError();
+}
+
 // ELL (Table 2): column of rule slot r of neuron i: row 0 = (i, -c), rows
 // 1..deg = (target, +p) for p > 0, the rest (-1, 0); stored row-major
 // [z+1][m] so that a row is contiguous over rules.

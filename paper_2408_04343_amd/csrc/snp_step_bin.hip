@@ -1,4 +1,4 @@
-// Binned push form of the step (OPTIMIZED, ELL, CSR_PUSH layouts) for gfx950.
+// Binned push form of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH layouts) for gfx950.
 //
 // The STEP of Algorithms 4 and 5 adds, for every emitting rule or neuron, its
 // spikes into the configuration of each target with atomics (Sec. 5).  Here a
@@ -130,9 +130,10 @@ __device__ __forceinline__ void bin_put(const BinLds& L, uint32_t* bc, int32_t t
 // ELL column `rule` from row 1, CSR row i from e0): target and value, target
 // -1 past the end of the row.
 template <int LAYOUT>
-__device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t rule, int32_t v, int32_t e0,
+__device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t rule, int32_t v, int64_t e0,
                                           int32_t jj) {
   if (LAYOUT == L_OPT) return make_int2(s.sy[(int64_t)jj * s.q + i], v);
+  if (LAYOUT == L_SLICED) return make_int2(s.sy[e0 + (int64_t)jj * SLICE], v);
   if (LAYOUT == L_ELL) return s.ell[(int64_t)(jj + 1) * s.m + rule];
   return make_int2(s.out_col[e0 + jj], v);
 }
@@ -140,7 +141,7 @@ __device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t ru
 // Entries j0, j0 + stride, ... below jend of one row; stops at the null entry.
 template <int LAYOUT>
 __device__ __forceinline__ void bin_walk(const SysDev& s, const BinLds& L, uint32_t* bc, int32_t i,
-                                         int32_t rule, int32_t v, int32_t e0, int32_t j0, int32_t stride,
+                                         int32_t rule, int32_t v, int64_t e0, int32_t j0, int32_t stride,
                                          int32_t jend) {
   for (int32_t jj = j0; jj < jend; jj += stride) {
     const int2 x = bin_entry<LAYOUT>(s, i, rule, v, e0, jj);
@@ -149,11 +150,22 @@ __device__ __forceinline__ void bin_walk(const SysDev& s, const BinLds& L, uint3
   }
 }
 
-// Row bound of a walk: the out-degree for CSR, the layout height for Sy and
-// ELL (their rows end at a null entry, or at the height).
+// Start and row bound of the walk of neuron i: CSR, its row start and
+// out-degree; sliced Sy, its column's first entry and the slice height;
+// Sy and ELL, the layout height (their rows end at a null entry, or there).
 template <int LAYOUT>
-__device__ __forceinline__ int32_t bin_height(const SysDev& s, int32_t deg) {
-  return LAYOUT == L_CSR_PUSH ? deg : s.z;
+__device__ __forceinline__ void bin_row(const SysDev& s, int32_t i, int64_t& e0, int32_t& jend) {
+  e0 = 0;
+  if (LAYOUT == L_CSR_PUSH) {
+    e0 = s.out_ptr[i];
+    jend = s.out_ptr[i + 1] - (int32_t)e0;
+  } else if (LAYOUT == L_SLICED) {
+    const int64_t b0 = s.sy_off[i / SLICE];
+    jend = (int32_t)((s.sy_off[i / SLICE + 1] - b0) / SLICE);
+    e0 = b0 + i % SLICE;
+  } else {
+    jend = s.z;
+  }
 }
 
 template <int LAYOUT, int RB, uint32_t FLAGS>
@@ -230,21 +242,15 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   // rest of each row up to BIN_LIGHT entries in batches of BIN_ROWS.  Longer
   // rows are finished below by the whole block.
   uint32_t* bc = pick(s.bins[0], s.bins[1], k);
-  int32_t e0[BIN_NPT], jend[BIN_NPT], rule[BIN_NPT];
+  int64_t e0[BIN_NPT];
+  int32_t jend[BIN_NPT], rule[BIN_NPT];
 #pragma unroll
   for (int r = 0; r < BIN_NPT; ++r) {
     const int32_t i = t0 + tid + r * BIN_NT;
     rule[r] = o[r].erule;
     e0[r] = 0;
     jend[r] = 0;
-    if (o[r].emit > 0) {
-      int32_t deg = 0;
-      if (LAYOUT == L_CSR_PUSH) {
-        e0[r] = s.out_ptr[i];
-        deg = s.out_ptr[i + 1] - e0[r];
-      }
-      jend[r] = bin_height<LAYOUT>(s, deg);
-    }
+    if (o[r].emit > 0) bin_row<LAYOUT>(s, i, e0[r], jend[r]);
   }
   bool more[BIN_NPT];
   {
@@ -298,7 +304,7 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
         // the entry keeps what the walk needs: the ELL column (rule slot) or
         // the value sent along Sy / CSR
         if (h < BIN_HMAX) L.heavy[h] = make_int2(i, LAYOUT == L_ELL ? rule[r] : o[r].emit);
-        else bin_walk<LAYOUT>(s, L, bc, i, rule[r], o[r].emit, e0[r], BIN_LIGHT, 1, deg);
+        else bin_walk<LAYOUT>(s, L, bc, i, rule[r], o[r].emit, e0[r], BIN_LIGHT, 1, min(deg, jend[r]));
       }
     }
   }
@@ -317,8 +323,11 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   for (int32_t h = 0; h < nh; ++h) {
     const int2 hv = L.heavy[h];
     const int32_t i = hv.x;
-    const int32_t ce0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - ce0;
-    bin_walk<LAYOUT>(s, L, bc, i, hv.y, hv.y, ce0, BIN_LIGHT + tid, BIN_NT, deg);
+    const int32_t deg = s.out_ptr[i + 1] - s.out_ptr[i];
+    int64_t ce0;
+    int32_t jh;
+    bin_row<LAYOUT>(s, i, ce0, jh);
+    bin_walk<LAYOUT>(s, L, bc, i, hv.y, hv.y, ce0, BIN_LIGHT + tid, BIN_NT, min(deg, jh));
   }
   __syncthreads();
   for (int32_t b = tid; b < nb; b += BIN_NT)
@@ -391,6 +400,7 @@ static hipError_t launch_bin_rf(const SysDev& s, int32_t j, hipStream_t st) {
   const size_t lds = bin_lds_bytes(s);
   switch (s.layout) {
     case L_OPT: step_bin_kernel<L_OPT, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
+    case L_SLICED: step_bin_kernel<L_SLICED, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     case L_ELL: step_bin_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     case L_CSR_PUSH: step_bin_kernel<L_CSR_PUSH, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     default: return hipErrorInvalidValue;
@@ -405,6 +415,9 @@ static hipError_t launch_bin_batch_rf(const SysDev& s, const SysDev* members, co
   switch (s.layout) {
     case L_OPT:
       step_bin_batch_kernel<L_OPT, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
+      break;
+    case L_SLICED:
+      step_bin_batch_kernel<L_SLICED, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
       break;
     case L_ELL:
       step_bin_batch_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);

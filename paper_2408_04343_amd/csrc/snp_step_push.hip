@@ -1,4 +1,4 @@
-// Push forms of the step (OPTIMIZED, ELL, CSR_PUSH layouts) for gfx950:
+// Push forms of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH layouts) for gfx950:
 // emitting neurons add their spikes into the receive buffer of the step.
 #include "snp_device.h"
 
@@ -59,6 +59,14 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
         atomicAdd(&cur[t], o.emit);
         ++deg;
       }
+    } else if (LAYOUT == L_SLICED) {
+      const int64_t b0 = s.sy_off[i / SLICE], h = (s.sy_off[i / SLICE + 1] - b0) / SLICE;
+      for (int64_t r = 0; r < h; ++r) {
+        const int32_t t = s.sy[b0 + r * SLICE + i % SLICE];
+        if (t < 0) break;
+        atomicAdd(&cur[t], o.emit);
+        ++deg;
+      }
     } else if (LAYOUT == L_ELL) {
       for (int32_t r = 1; r <= s.z; ++r) {
         const int2 pr = s.ell[(int64_t)r * s.m + o.erule];
@@ -113,6 +121,7 @@ static hipError_t launch_push_rf(const SysDev& s, int32_t j, hipStream_t st) {
   const dim3 grid((s.q + PUSH_NT - 1) / PUSH_NT);
   switch (s.layout) {
     case L_OPT: step_push_kernel<L_OPT, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
+    case L_SLICED: step_push_kernel<L_SLICED, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     case L_ELL: step_push_kernel<L_ELL, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     case L_CSR_PUSH: step_push_kernel<L_CSR_PUSH, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     default: return hipErrorInvalidValue;
@@ -125,6 +134,9 @@ static hipError_t launch_push_batch_rf(const SysDev& s, const SysDev* members, c
                                        const int32_t* ntiles, int32_t grid, int32_t j, hipStream_t st) {
   switch (s.layout) {
     case L_OPT: step_push_batch_kernel<L_OPT, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j); break;
+    case L_SLICED:
+      step_push_batch_kernel<L_SLICED, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j);
+      break;
     case L_ELL: step_push_batch_kernel<L_ELL, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j); break;
     case L_CSR_PUSH:
       step_push_batch_kernel<L_CSR_PUSH, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j);

@@ -39,6 +39,7 @@ def test_footprint_orders():
     q, m, nnz, z = 1 << 20, 2621440, 16777216, 39
     pull = binding.footprint(q, m, nnz, z, "csr_pull")
     opt = binding.footprint(q, m, nnz, z, "optimized")
+    assert binding.footprint(q, m, nnz, z, "sliced") <= opt
     ell = binding.footprint(q, m, nnz, z, "ell")
     assert 0 < pull < opt < ell
     # ELL stores z'+1 (neuron, value) pairs per rule

@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 # emitted values from device memory (plain "csr_pull" stages them in LDS at
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
 # device-wide atomic adds
-LAYOUTS = ["csr_pull", "csr_pull_gather", "optimized", "ell", "csr_push",
-           "optimized_atomic", "ell_atomic", "csr_push_atomic"]
+LAYOUTS = ["csr_pull", "csr_pull_gather", "optimized", "sliced", "ell", "csr_push",
+           "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
 
 
 def lk(layout):
@@ -126,6 +126,8 @@ def test_layouts_built_on_device_match_tables(binding):
     g = binding.System.from_spec(spec, layout="optimized")
     sy = g.read_layout("optimized").reshape(3, 9)
     assert sy.tolist() == int_matrix("table3_sort3_sy.txt")
+    g = binding.System.from_spec(spec, layout="sliced")
+    assert g.read_layout("sliced").reshape(3, 9).tolist() == int_matrix("table3_sort3_sy.txt")
     g = binding.System.from_spec(spec, layout="ell")
     ell = g.read_layout("ell").reshape(4, 12, 2)
     nid, val = oracle_of(spec, orc.SEM_STANDARD).ell()   # pinned to Table 2
@@ -137,6 +139,12 @@ def test_device_layouts_match_oracle_on_random_system(binding):
     o = oracle_of(spec, orc.SEM_STANDARD)
     g = binding.System.from_spec(spec, layout="optimized")
     assert np.array_equal(g.read_layout("optimized").reshape(o.sy().shape), o.sy())
+    # slices of 64 neurons, each as tall as its largest out-degree, expand to Sy
+    h = binding.System.from_spec(spec, layout="sliced")
+    assert np.array_equal(h.read_layout("sliced").reshape(o.sy().shape), o.sy())
+    deg = np.bincount(spec.src, minlength=spec.q)
+    heights = [deg[b:b + 64].max() for b in range(0, spec.q, 64)]
+    assert h.info()["device_bytes"] < g.info()["device_bytes"] or max(heights) == min(heights)
     g = binding.System.from_spec(spec, layout="ell")
     nid, val = o.ell()
     ell = g.read_layout("ell").reshape(nid.shape[0], nid.shape[1], 2)
@@ -269,7 +277,7 @@ def _heavy_spec(n_heavy, hub_deg, q=6000, seed=21):
                       wl.SELECT_HASH, 5, 12)
 
 
-@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push"])
+@pytest.mark.parametrize("layout", ["optimized", "sliced", "ell", "csr_push"])
 @pytest.mark.parametrize("n_heavy", [40, 1100])
 def test_binned_heavy_rows(binding, layout, n_heavy):
     # rows longer than a thread walks alone go to the block; more heavy
@@ -337,7 +345,7 @@ def _batch_specs(n, seed=0, qmax=9000):
                             dmax=3, c0max=8, select=wl.SELECT_HASH) for j, q in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_push", "optimized", "ell",
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_push", "optimized", "sliced", "ell",
                                     "csr_push_atomic"])
 def test_batch_equals_alone(binding, layout):
     specs = _batch_specs(14, seed=1)
@@ -449,7 +457,7 @@ def test_config2_full_size_digests(binding):
     assert np.array_equal(g.read_spiking(), r["S"])
 
 
-@pytest.mark.parametrize("layout", ["optimized", "ell", "csr_push", "csr_push_atomic"])
+@pytest.mark.parametrize("layout", ["optimized", "sliced", "ell", "csr_push", "csr_push_atomic"])
 def test_config2_full_size_push_layouts(binding, layout):
     spec = wl.config2(steps=40)
     ref = oracle_of(spec, orc.SEM_STANDARD).step_record(40, want_state=False)
