@@ -360,7 +360,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--skewed", action="store_true", help="also measure the skewed-degree workload")
+    ap.add_argument("--no-skewed", action="store_true", help="skip the skewed-degree workload")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
@@ -420,7 +420,7 @@ def main():
     batched = None
     if not args.no_batch:
         batched = run_batched(binding, torch, scale=args.batch_scale)
-    skewed = run_skewed(binding, torch) if args.skewed else None
+    skewed = None if args.no_skewed else run_skewed(binding, torch)
     served = None
     if not args.no_serve:
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
