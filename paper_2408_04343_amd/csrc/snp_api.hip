@@ -57,7 +57,7 @@ int64_t pull_lds_budget(int32_t) { return kPullLdsBytes; }
 // padding 0xFFFFFFFF.
 int32_t pull_chunk_sources(int32_t w, int32_t tb) {
   const int64_t tile = 1LL << tb;
-  const int64_t fixed = tile * 4 + tile * w / 8 + 2048;
+  const int64_t fixed = tile * 4 + tile * w / 8 + tile * 2 + 2048;
   int64_t src = (pull_lds_budget(tb) - fixed) * 8 / w;
   src = std::min<int64_t>(src, (1LL << (32 - tb)) - 128);
   src -= src % 128;  // chunk starts stay 16-byte aligned in the emit vector
@@ -534,6 +534,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     if (o.emit_bits < d.emit_w) return bail(fail(SNP_EINVAL, "emit_bits too small for the largest p"));
     d.emit_w = o.emit_bits;
   }
+  d.sel_wave = maxr > SEL_LIGHT_RULES ? 1 : 0;
   d.pull_gather = pull_gathers(o.pull_mode, q, nsyn, d.emit_w) ? 1 : 0;
   d.pull_tb = d.pull_gather ? PULL_TB_GATHER : PULL_TB_STAGED;
   d.pull_chunk = d.pull_gather ? pull_gather_chunk(d.pull_tb) : pull_chunk_sources(d.emit_w, d.pull_tb);

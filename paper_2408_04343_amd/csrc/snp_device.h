@@ -239,14 +239,19 @@ struct Sel {
   bool act;       // neuron is active in state k (closed, or has an applicable rule)
 };
 
+// `chosen`: the rule slot chosen beforehand by wave_choose (-1 none), or
+// CHOOSE_HERE to choose now.
+constexpr int32_t CHOOSE_HERE = -2;
+
 template <int RB, bool CNT>
 __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k,
-                                             const NeuronIn<RB>& in, Cnt& cnt) {
+                                             const NeuronIn<RB>& in, Cnt& cnt,
+                                             int32_t chosen = CHOOSE_HERE) {
   const int32_t D = (int32_t)(in.meta & META_D);
   int32_t Dn = 0, cons = 0, sel = -1;
   Sel o{0, -1, false};
   if (D == 0) {
-    sel = choose_rule<RB>(s, i, k, in);
+    sel = chosen == CHOOSE_HERE ? choose_rule<RB>(s, i, k, in) : chosen;
     if (CNT) {
       cnt.v[C_OPEN] += 1;
       cnt.v[C_RULES] += (unsigned long long)(in.r1 - in.r0);
@@ -286,6 +291,71 @@ __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t
   pick(s.S16[0], s.S16[1], k)[i] = sel >= 0 ? (uint16_t)(sel - in.r0) : S_NONE;
   if (CNT && o.emit > 0) cnt.v[C_EMIT] += 1;
   return o;
+}
+
+// ------------------------------------------- selection over many rules --
+//
+// A neuron with more than SEL_LIGHT_RULES rules (the sorting family of Sec. 6 gives
+// n rules to each of its n sorting neurons) is not scanned by its own thread:
+// a whole wave evaluates 64 of its rules per load (neighbouring lanes read
+// neighbouring records) and combines the results with ballots.
+
+template <int RB>
+__device__ __forceinline__ bool defer_select(const SysDev& s, const NeuronIn<RB>& in) {
+  return s.sel_wave && (in.meta & META_D) == 0 && in.r1 - in.r0 > SEL_LIGHT_RULES;
+}
+
+// Rule chosen by open neuron i holding n spikes at step k (FIRST: the lowest
+// applicable slot; HASH: the j-th applicable one, j from the same hash as
+// choose_rule), or -1.  Called by all 64 lanes of a wave with the same
+// arguments; every lane returns the result.
+template <int RB>
+__device__ __forceinline__ int32_t wave_choose(const SysDev& s, int32_t i, int64_t k, int32_t n,
+                                               int32_t r0, int32_t r1) {
+  const int lane = threadIdx.x & 63;
+  if (s.sel == SEL_FIRST) {
+    for (int32_t b = r0; b < r1; b += 64) {
+      const int32_t r = b + lane;
+      const bool ok = r < r1 && rule_applies(load_rule<RB>(s, r), n);
+      const unsigned long long m = __ballot(ok);
+      if (m) return b + __ffsll((long long)m) - 1;
+    }
+    return -1;
+  }
+  uint32_t cnt = 0;
+  for (int32_t b = r0; b < r1; b += 64) {
+    const int32_t r = b + lane;
+    cnt += (uint32_t)__popcll(__ballot(r < r1 && rule_applies(load_rule<RB>(s, r), n)));
+  }
+  if (cnt == 0) return -1;
+  const uint64_t key = ((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)i;
+  const uint64_t h = mix64(mix64(s.seed) ^ key);
+  uint32_t j = (uint32_t)(((h >> 32) * (uint64_t)cnt) >> 32);
+  for (int32_t b = r0; b < r1; b += 64) {
+    const int32_t r = b + lane;
+    unsigned long long m = __ballot(r < r1 && rule_applies(load_rule<RB>(s, r), n));
+    const uint32_t c = (uint32_t)__popcll(m);
+    if (j < c) {
+      for (uint32_t x = 0; x < j; ++x) m &= m - 1;  // drop the j lowest applicable slots
+      return b + __ffsll((long long)m) - 1;
+    }
+    j -= c;
+  }
+  return -1;
+}
+
+// The waves of a block choose the rules of the deferred neurons list[0..nl):
+// local index lt holds its spike count in val[lt] on entry and the chosen
+// slot (-1 none) on exit.
+template <int RB, int NT>
+__device__ __forceinline__ void wave_select_pass(const SysDev& s, int32_t t0, int64_t k, int32_t* val,
+                                                 const uint16_t* list, int32_t nl) {
+  for (int32_t d = threadIdx.x >> 6; d < nl; d += NT / 64) {
+    const int32_t lt = list[d];
+    const int32_t t = t0 + lt;
+    const int32_t sel = wave_choose<RB>(s, t, k, val[lt], s.rs[t], s.rs[t + 1]);
+    if ((threadIdx.x & 63) == 0) val[lt] = sel;
+  }
 }
 
 // Caller id of the rule recorded for neuron i in S16[buf], or -1.

@@ -20,6 +20,7 @@ constexpr uint16_t S_NONE = 0xFFFFu;
 constexpr int NCOUNT = 10;  // fields of snp_counters
 constexpr int32_t PULL_TB_STAGED = 12;  // log2 neurons per pull tile, staged reception
 constexpr int32_t PULL_TB_GATHER = 10;  // log2 neurons per pull tile, gather reception
+constexpr int32_t SEL_LIGHT_RULES = 32;  // rules a thread scans alone; more: a wave per neuron
 constexpr int32_t BIN_TB = 12;          // log2 neurons per tile of the binned push
 constexpr int32_t BIN_MAX_TILES = 2048; // binned push up to 2048 tiles (8,388,608 neurons)
 
@@ -68,6 +69,7 @@ struct SysDev {
   // rule vector, neuron-rule map
   const int32_t* rs;         // [q+1] rules of neuron i: slots rs[i] .. rs[i+1]-1
   int32_t rule_bytes;        // 8: rules8 holds the rule vector, 16: rules does
+  int32_t sel_wave;          // 1: some neuron has more rules than a thread scans alone
   const RuleRec* rules;      // [m] in slot order
   const uint2* rules8;       // [m] in slot order, packed
   const int32_t* rid;        // [m] caller id of each slot

@@ -55,6 +55,7 @@ struct BinLds {
   int32_t* offp;
   int32_t* lcnt;
   int2* heavy;
+  uint16_t* defer;   // [BIN_TILE] neurons whose rules a wave scans
 };
 
 __device__ __forceinline__ BinLds bin_lds(uint32_t* lds, int32_t nb) {
@@ -66,12 +67,13 @@ __device__ __forceinline__ BinLds bin_lds(uint32_t* lds, int32_t nb) {
   L.lcnt = L.offp + nb;
   const int32_t used = BIN_TILE + 4 * nb + 1;
   L.heavy = (int2*)((int32_t*)lds + ((used + 1) & ~1));
+  L.defer = (uint16_t*)(L.heavy + BIN_HMAX);
   return L;
 }
 
 size_t bin_lds_bytes(const SysDev& s) {
   const int64_t used = BIN_TILE + 4LL * s.bnb + 1;
-  return (size_t)(4 * ((used + 1) & ~1LL) + 8 * BIN_HMAX);
+  return (size_t)(4 * ((used + 1) & ~1LL) + 8 * BIN_HMAX + 2 * BIN_TILE);
 }
 
 // Sums into L.acc (zeroed by the caller, before the first barrier here) the
@@ -170,7 +172,8 @@ __device__ __forceinline__ void bin_row(const SysDev& s, int32_t i, int64_t& e0,
 
 template <int LAYOUT, int RB, uint32_t FLAGS>
 __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t j, uint32_t* lds,
-                                         unsigned long long* red, int32_t* wsum, int32_t* hcount) {
+                                         unsigned long long* red, int32_t* wsum, int32_t* hcount,
+                                         int32_t* ndefer) {
   constexpr bool DIG = (FLAGS & F_DIGEST) != 0;
   constexpr bool CNT = (FLAGS & F_COUNTERS) != 0;
   const BinLds L = bin_lds(lds, s.bnb);
@@ -197,7 +200,10 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     L.offp[b] = s.boffp[(size_t)tile * nb + b];
     L.lcnt[b] = 0;
   }
-  if (tid == 0) *hcount = 0;
+  if (tid == 0) {
+    *hcount = 0;
+    *ndefer = 0;
+  }
   if (k > 0) bin_receive(s, tile, (int32_t)((k - 1) & 1), L, wsum);
   __syncthreads();
 
@@ -230,8 +236,28 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     in[r].C = C;
     if (DIG && k > 0)
       dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
+    if (defer_select<RB>(s, in[r])) {
+      L.acc[lt] = C;  // the reception has been read: the slot carries the count to the wave
+      L.defer[atomicAdd(ndefer, 1)] = (uint16_t)lt;
+      continue;
+    }
     o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt);
     anyact |= o[r].act;
+  }
+  if (s.sel_wave) {
+    // neurons with many rules: a wave per neuron chooses, the owner applies
+    __syncthreads();
+    wave_select_pass<RB, BIN_NT>(s, t0, k, L.acc, L.defer, *ndefer);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BIN_NPT; ++r) {
+      const int32_t lt = tid + r * BIN_NT;
+      const int32_t t = t0 + lt;
+      if (t < s.q && defer_select<RB>(s, in[r])) {
+        o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt, L.acc[lt]);
+        anyact |= o[r].act;
+      }
+    }
   }
   const unsigned long long am = __ballot(anyact);
   if (am && (tid & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;
@@ -354,8 +380,8 @@ __global__ void __launch_bounds__(BIN_NT) step_bin_kernel(SysDev s, int32_t j) {
   extern __shared__ uint4 lds4[];
   __shared__ unsigned long long red[BIN_NT / 64];
   __shared__ int32_t wsum[BIN_NT / 64 + 1];
-  __shared__ int32_t hcount;
-  bin_body<LAYOUT, RB, FLAGS>(s, blockIdx.x, j, (uint32_t*)lds4, red, wsum, &hcount);
+  __shared__ int32_t hcount, ndefer;
+  bin_body<LAYOUT, RB, FLAGS>(s, blockIdx.x, j, (uint32_t*)lds4, red, wsum, &hcount, &ndefer);
 }
 
 // Batched form: block b runs tile tiles[b].y of system members[tiles[b].x].
@@ -366,11 +392,11 @@ __global__ void __launch_bounds__(BIN_NT)
   extern __shared__ uint4 lds4[];
   __shared__ unsigned long long red[BIN_NT / 64];
   __shared__ int32_t wsum[BIN_NT / 64 + 1];
-  __shared__ int32_t hcount;
+  __shared__ int32_t hcount, ndefer;
   if ((int32_t)blockIdx.x >= *ntiles) return;
   const int2 tm = tiles[blockIdx.x];
   const SysDev s = members[tm.x];
-  bin_body<LAYOUT, RB, FLAGS>(s, tm.y, j, (uint32_t*)lds4, red, wsum, &hcount);
+  bin_body<LAYOUT, RB, FLAGS>(s, tm.y, j, (uint32_t*)lds4, red, wsum, &hcount, &ndefer);
 }
 
 // Per-target sums of the records in buffer rbuf (reads of a state whose

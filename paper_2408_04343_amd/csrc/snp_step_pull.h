@@ -24,7 +24,7 @@ constexpr int PULL_NPT = 4;              // neurons per thread
 // are loaded before the reception so that their latency overlaps it.
 template <int TB, int W, int RB, uint32_t FLAGS, bool GATHER>
 __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t j, uint32_t* lds,
-                                          unsigned long long* red) {
+                                          unsigned long long* red, int32_t* ndefer) {
   constexpr int PULL_TILE = 1 << TB;
   constexpr int PULL_NT = PULL_TILE / PULL_NPT;
   constexpr int PULL_TBITS = TB;
@@ -34,7 +34,8 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   constexpr int TILE_WORDS = PULL_TILE * W / 32;
   int32_t* acc = (int32_t*)lds;              // [PULL_TILE] spikes received by each neuron
   uint32_t* stage = lds + PULL_TILE;         // [TILE_WORDS] emitted values of this tile
-  uint32_t* chunk = stage + TILE_WORDS;      // emitted values of one source chunk (16-byte aligned)
+  uint16_t* defer = (uint16_t*)(stage + TILE_WORDS);  // [PULL_TILE] neurons whose rules a wave scans
+  uint32_t* chunk = stage + TILE_WORDS + PULL_TILE / 2;  // emitted values of one source chunk (16-byte aligned)
   int64_t k;
   if (!step_prologue(s, tile, j, k)) return;
   const int32_t t0 = tile * PULL_TILE;
@@ -54,6 +55,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     acc[tid + r * PULL_NT] = 0;
   }
   for (int w = tid; w < TILE_WORDS; w += PULL_NT) stage[w] = 0u;
+  if (tid == 0) *ndefer = 0;
 
   if (GATHER && k > 0) {
     // GATHER: one pass over all in-edges of the tile; every edge reads its
@@ -162,6 +164,20 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   cnt.zero();
   unsigned long long dig = 0;
   bool anyact = false;
+  // activity, packed emitted value and counters of one neuron's step
+  auto emit_one = [&](int r, const Sel& o) {
+    const int32_t lt = tid + r * PULL_NT;
+    anyact |= o.act;
+    if (o.emit > 0) {
+      const uint32_t off = (uint32_t)lt * W;
+      atomicOr(&stage[off >> 5], ((uint32_t)o.emit & VMASK) << (off & 31));
+      if (CNT) {
+        const unsigned long long dg = (unsigned long long)s.out_deg[t0 + lt];
+        cnt.v[C_EDGES] += dg;
+        cnt.v[C_SENT] += dg * (unsigned long long)o.emit;
+      }
+    }
+  };
 #pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
     const int32_t lt = tid + r * PULL_NT;
@@ -185,16 +201,23 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     in[r].C = C;
     if (DIG && k > 0)
       dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
-    const Sel o = select_update<RB, CNT>(s, t, k, in[r], cnt);
-    anyact |= o.act;
-    if (o.emit > 0) {
-      const uint32_t off = (uint32_t)lt * W;
-      atomicOr(&stage[off >> 5], ((uint32_t)o.emit & VMASK) << (off & 31));
-      if (CNT) {
-        const unsigned long long dg = (unsigned long long)s.out_deg[t];
-        cnt.v[C_EDGES] += dg;
-        cnt.v[C_SENT] += dg * (unsigned long long)o.emit;
-      }
+    if (defer_select<RB>(s, in[r])) {
+      acc[lt] = C;  // the reception has been read: the slot carries the count to the wave
+      defer[atomicAdd(ndefer, 1)] = (uint16_t)lt;
+      continue;
+    }
+    emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt));
+  }
+  if (s.sel_wave) {
+    // neurons with many rules: a wave per neuron chooses, the owner applies
+    __syncthreads();
+    wave_select_pass<RB, PULL_NT>(s, t0, k, acc, defer, *ndefer);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PULL_NPT; ++r) {
+      const int32_t lt = tid + r * PULL_NT;
+      const int32_t t = t0 + lt;
+      if (t < s.q && defer_select<RB>(s, in[r])) emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt, acc[lt]));
     }
   }
   const unsigned long long am = __ballot(anyact);
@@ -219,7 +242,8 @@ template <int TB, int W, int RB, uint32_t FLAGS, bool GATHER>
 __global__ void __launch_bounds__((1 << TB) / PULL_NPT) step_pull_kernel(SysDev s, int32_t j) {
   extern __shared__ uint4 lds4[];
   __shared__ unsigned long long red[(1 << TB) / PULL_NPT / 64];
-  pull_body<TB, W, RB, FLAGS, GATHER>(s, blockIdx.x, j, (uint32_t*)lds4, red);
+  __shared__ int32_t ndefer;
+  pull_body<TB, W, RB, FLAGS, GATHER>(s, blockIdx.x, j, (uint32_t*)lds4, red, &ndefer);
 }
 
 // Batched form: block b runs tile tiles[b].y of system members[tiles[b].x].
@@ -229,10 +253,11 @@ __global__ void __launch_bounds__((1 << TB) / PULL_NPT)
                            const int32_t* __restrict__ ntiles, int32_t j) {
   extern __shared__ uint4 lds4[];
   __shared__ unsigned long long red[(1 << TB) / PULL_NPT / 64];
+  __shared__ int32_t ndefer;
   if ((int32_t)blockIdx.x >= *ntiles) return;
   const int2 tm = tiles[blockIdx.x];
   const SysDev s = members[tm.x];
-  pull_body<TB, W, RB, FLAGS, GATHER>(s, tm.y, j, (uint32_t*)lds4, red);
+  pull_body<TB, W, RB, FLAGS, GATHER>(s, tm.y, j, (uint32_t*)lds4, red, &ndefer);
 }
 
 

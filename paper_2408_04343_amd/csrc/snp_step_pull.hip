@@ -9,7 +9,7 @@ size_t pull_lds_bytes(const SysDev& s) {
   const int64_t tile = 1LL << s.pull_tb;
   const int64_t csz = std::min<int64_t>(s.pull_chunk, ((int64_t)s.q + 127) / 128 * 128);
   const int64_t cwords = s.pull_gather ? 0 : ((csz * s.emit_w + 31) / 32 + 3) / 4 * 4;
-  return (size_t)(tile * 4 + tile * s.emit_w / 32 * 4 + cwords * 4);
+  return (size_t)(tile * 4 + tile * s.emit_w / 32 * 4 + tile * 2 + cwords * 4);
 }
 
 // Lets the staged pull kernels use up to `bytes` of dynamic LDS (the gather

@@ -39,7 +39,8 @@ def test_footprint_orders():
     q, m, nnz, z = 1 << 20, 2621440, 16777216, 39
     pull = binding.footprint(q, m, nnz, z, "csr_pull")
     opt = binding.footprint(q, m, nnz, z, "optimized")
-    assert binding.footprint(q, m, nnz, z, "sliced") <= opt
+    # slices never take more than the global Sy, plus their offsets
+    assert binding.footprint(q, m, nnz, z, "sliced") <= opt + 8 * (q // 64 + 2) + 256
     ell = binding.footprint(q, m, nnz, z, "ell")
     assert 0 < pull < opt < ell
     # ELL stores z'+1 (neuron, value) pairs per rule

@@ -120,6 +120,29 @@ def test_sort_family_closed_form(binding, layout):
         g.close()
 
 
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "sliced", "ell"])
+def test_sort_family_many_rules(binding, layout):
+    # 700 rules on each sorting neuron: a wave scans them 64 at a time
+    rng = np.random.default_rng(12)
+    v = rng.integers(1, 400, size=700).tolist()
+    spec = wl.sort_system(v)
+    g = binding.System.from_spec(spec, **lk(layout))
+    g.step(10_000)
+    assert g.steps_done() == (max(v) + 1, True)
+    C = g.read_config()
+    assert C[1400:].tolist() == sorted(v) and not C[:1400].any()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("select", ["first", "hash"])
+def test_many_rules_every_step(binding, layout, select):
+    # 0..200 rules per neuron, many applicable at once: the HASH choice picks
+    # the j-th applicable rule across several groups of 64
+    spec = wl.small_random(31, 1500, max_deg=6, max_rules=200, dmax=2, c0max=12,
+                           select=wl.SELECT_HASH if select == "hash" else wl.SELECT_FIRST, steps=20)
+    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 20)
+
+
 def test_layouts_built_on_device_match_tables(binding):
     from tests._golden import int_matrix
     spec = wl.sort_system([3, 1, 2])
