@@ -248,6 +248,49 @@ def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optim
     return out
 
 
+def run_sort(binding, torch, sizes=(100, 1000, 5000), layouts=("csr_pull", "sliced"), push_max_n=1000):
+    """The paper's sorting family (Sec. 6, Table 1): n inputs v ~ U{1..n},
+    q = 3n neurons, n + n^2 rules (n on each sorting neuron), 1.5 n^2
+    synapses; runs to halting (max(v) + 1 steps) and checks the closed form
+    (outputs sorted, inputs and sorting neurons empty)."""
+    from paper_2408_04343_amd import workloads as wl
+    out = []
+    for n in sizes:
+        v = np.random.default_rng([6, n]).integers(1, n + 1, size=n)
+        t0 = time.time()
+        spec = wl.sort_system(v)
+        gen_s = time.time() - t0
+        for lay in layouts:
+            if lay != "csr_pull" and n > push_max_n:
+                continue   # the push layouts run a block per 4096 neurons: minutes at this size
+            t0 = time.time()
+            g = binding.System.from_spec(spec, layout=lay)
+            create_s = time.time() - t0
+            stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            g.step(int(v.max()) + 1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            steps, halted = g.steps_done()
+            C = g.read_config()
+            ok = bool(halted and steps == int(v.max()) + 1 and np.array_equal(C[2 * n:], np.sort(v))
+                      and not C[:2 * n].any())
+            info = g.info()
+            g.close()
+            r = {"n": n, "layout": lay, "q": spec.q, "rules": spec.m, "synapses": spec.nnz, "steps": int(steps),
+                 "pull_mode": info["pull_mode"], "push_mode": info["push_mode"],
+                 "ms_total": round(ms, 3), "us_per_step": round(1e3 * ms / max(steps, 1), 3),
+                 "neuron_updates_per_s": spec.q * steps / (ms * 1e-3),
+                 "closed_form_ok": ok, "gen_s": round(gen_s, 1), "create_s": round(create_s, 1)}
+            out.append(r)
+            log("sort n=%d %-8s %d steps %.3f ms (%.2f us/step) closed form %s" %
+                (n, lay, steps, ms, r["us_per_step"], "ok" if ok else "WRONG"))
+    return out
+
+
 def cpu_baseline(spec, seconds):
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
@@ -361,6 +404,8 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-skewed", action="store_true", help="skip the skewed-degree workload")
+    ap.add_argument("--sort-n", default="100,1000,5000",
+                    help="sizes of the sorting family run to halting ('' to skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
@@ -421,6 +466,8 @@ def main():
     if not args.no_batch:
         batched = run_batched(binding, torch, scale=args.batch_scale)
     skewed = None if args.no_skewed else run_skewed(binding, torch)
+    sort_sizes = [int(x) for x in args.sort_n.split(",") if x]
+    sorting = run_sort(binding, torch, sort_sizes) if sort_sizes else None
     served = None
     if not args.no_serve:
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
@@ -444,6 +491,7 @@ def main():
         "batched_vs_plain": batched,
         "served": served,
         "skewed": skewed,
+        "sorting_family": sorting,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
                                 "over": "graph chunks of %d steps" % args.chunk},
         "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()

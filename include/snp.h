@@ -95,6 +95,14 @@ extern "C" {
 #define SNP_PULL_AUTO   0
 #define SNP_PULL_STAGED 1
 #define SNP_PULL_GATHER 2
+/* WIDE: for few neurons with very many in-edges and rules each (the sorting
+ * family: q = 3n, n in-edges and n rules per sorting neuron), where a block
+ * per tile leaves most of the GPU idle.  Three launches per step: one wave
+ * per neuron sums its in-edges, one wave per neuron with more than 32 rules
+ * chooses among them, then the tile kernel finishes the step.  AUTO picks it
+ * above 256 K in-edges per 4096 neurons.  Systems in this mode are not
+ * accepted by snp_batch_* (SNP_ENOTSUP).                                   */
+#define SNP_PULL_WIDE   3
 
 /* Push layouts.  ATOMIC: every synapse of an emitting neuron adds its
  * spikes to the target's count with a device-wide atomic, as the STEP of
@@ -259,7 +267,7 @@ typedef struct snp_info_t {
   int32_t pull_tile_log2;/* CSR_PULL: log2 of the neurons per block          */
   int32_t pull_chunk;    /* CSR_PULL: sources per LDS chunk                  */
   int32_t pull_chunks;   /* CSR_PULL: number of source chunks                */
-  int32_t pull_mode;     /* CSR_PULL: SNP_PULL_STAGED or SNP_PULL_GATHER     */
+  int32_t pull_mode;     /* CSR_PULL: SNP_PULL_STAGED, _GATHER or _WIDE      */
   int32_t push_mode;     /* push layouts: SNP_PUSH_ATOMIC or SNP_PUSH_BINNED */
   int32_t reserved;
   int64_t device_bytes;  /* device memory held by the handle                 */

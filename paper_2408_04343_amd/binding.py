@@ -25,8 +25,8 @@ LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL
            "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL, "sliced": LAYOUT_SLICED}
 SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
 SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
-PULL_AUTO, PULL_STAGED, PULL_GATHER = 0, 1, 2
-PULL_MODES = {"auto": PULL_AUTO, "staged": PULL_STAGED, "gather": PULL_GATHER}
+PULL_AUTO, PULL_STAGED, PULL_GATHER, PULL_WIDE = 0, 1, 2, 3
+PULL_MODES = {"auto": PULL_AUTO, "staged": PULL_STAGED, "gather": PULL_GATHER, "wide": PULL_WIDE}
 PUSH_AUTO, PUSH_ATOMIC, PUSH_BINNED = 0, 1, 2
 PUSH_MODES = {"auto": PUSH_AUTO, "atomic": PUSH_ATOMIC, "binned": PUSH_BINNED}
 

@@ -71,6 +71,14 @@ int32_t pull_gather_chunk(int32_t tb) { return (int32_t)((1LL << (32 - tb)) - 12
 // AUTO: staging copies the whole emit vector into every block, gathering
 // costs one scattered load per in-edge; gather when a block's in-edges are
 // fewer than half the words of the emit vector.
+// AUTO: wide above 256 K in-edges per 4096-neuron tile (a block per tile
+// would stream them alone).
+bool pull_wide(int32_t mode, int32_t q, int64_t nsyn) {
+  if (mode != SNP_PULL_AUTO) return mode == SNP_PULL_WIDE;
+  const int64_t tiles = ((int64_t)q + (1LL << PULL_TB_STAGED) - 1) >> PULL_TB_STAGED;
+  return nsyn / tiles > 262144;
+}
+
 bool pull_gathers(int32_t mode, int32_t q, int64_t nsyn, int32_t w) {
   if (mode != SNP_PULL_AUTO) return mode == SNP_PULL_GATHER;
   const int64_t tiles = ((int64_t)q + (1LL << PULL_TB_STAGED) - 1) >> PULL_TB_STAGED;
@@ -117,6 +125,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
       best = std::max(best, x.bytes);
     }
     p.bytes += best;
+    p.add(12LL * q);           // wide schedule: receptions, choices, many-rule list
     p.add(4LL * (q + 1));
     p.add(4LL * std::max<int64_t>(nnz, 1));
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
@@ -285,12 +294,17 @@ int alloc_state(snp_sys* s, const int32_t* spikes0) {
     if ((st = alloc_fill(s, (void**)&d.counters, 8 * NCOUNT * (size_t)(d.ring + 1), 0)) != SNP_OK) return st;
   d.emit[0] = d.emit[1] = nullptr;
   d.delta[0] = d.delta[1] = nullptr;
+  d.recv = d.hsel = nullptr;
   if (d.layout == L_CSR_PULL) {
     const size_t tile = (size_t)1 << d.pull_tb;
     const size_t tiles = ((size_t)q + tile - 1) / tile;
     const size_t words = tiles * tile * d.emit_w / 32;
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.emit[b], 4 * words, 0)) != SNP_OK) return st;
+    if (d.pull_wide) {
+      if ((st = alloc_fill(s, (void**)&d.recv, 4 * (size_t)q, 0)) != SNP_OK) return st;
+      if ((st = alloc_fill(s, (void**)&d.hsel, 4 * (size_t)q, 0xFF)) != SNP_OK) return st;
+    }
   } else {
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return st;
@@ -371,7 +385,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   if (o.layout == SNP_LAYOUT_AUTO) o.layout = SNP_LAYOUT_CSR_PULL;
   if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_SLICED) return fail(SNP_EINVAL, "bad layout");
   if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
-  if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_GATHER) return fail(SNP_EINVAL, "bad pull_mode");
+  if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_WIDE) return fail(SNP_EINVAL, "bad pull_mode");
   if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_BINNED) return fail(SNP_EINVAL, "bad push_mode");
   if (o.semantics != SNP_SEM_STANDARD && o.semantics != SNP_SEM_PAPER_KERNEL)
     return fail(SNP_EINVAL, "bad semantics");
@@ -535,8 +549,9 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.emit_w = o.emit_bits;
   }
   d.sel_wave = maxr > SEL_LIGHT_RULES ? 1 : 0;
-  d.pull_gather = pull_gathers(o.pull_mode, q, nsyn, d.emit_w) ? 1 : 0;
-  d.pull_tb = d.pull_gather ? PULL_TB_GATHER : PULL_TB_STAGED;
+  d.pull_wide = pull_wide(o.pull_mode, q, nsyn) ? 1 : 0;
+  d.pull_gather = !d.pull_wide && pull_gathers(o.pull_mode, q, nsyn, d.emit_w) ? 1 : 0;
+  d.pull_tb = (d.pull_gather || d.pull_wide) ? PULL_TB_GATHER : PULL_TB_STAGED;
   d.pull_chunk = d.pull_gather ? pull_gather_chunk(d.pull_tb) : pull_chunk_sources(d.emit_w, d.pull_tb);
 
   int st;
@@ -580,7 +595,17 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.in_ptr = p;
     if ((st = upload(s, &p, s->h_in_src.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
     d.in_src = p;
-    {
+    if (d.pull_wide) {
+      // no blocked in-edges: reception walks the in-lists; many-rule neurons listed
+      d.pull_nc = 0;
+      d.pull_chunk = 0;
+      std::vector<int32_t> hv;
+      for (int32_t i = 0; i < q; ++i)
+        if (rs[(size_t)i + 1] - rs[i] > SEL_LIGHT_RULES) hv.push_back(i);
+      if ((st = upload(s, &p, hv.data(), hv.size())) != SNP_OK) return bail(st);
+      d.heavy = p;
+      d.n_heavy = (int32_t)hv.size();
+    } else {
       // in-edges blocked by (target tile, source chunk), each segment sorted
       const int64_t T = 1LL << d.pull_tb, CS = d.pull_chunk;
       const int64_t nb = ((int64_t)q + T - 1) / T, nc = ((int64_t)q + CS - 1) / CS;
@@ -993,7 +1018,9 @@ int snp_info(snp_sys* s, snp_info_t* o) {
   o->pull_tile_log2 = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_tb : 0;
   o->pull_chunk = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_chunk : 0;
   o->pull_chunks = s->layout == SNP_LAYOUT_CSR_PULL ? s->d.pull_nc : 0;
-  o->pull_mode = s->layout != SNP_LAYOUT_CSR_PULL ? 0 : s->d.pull_gather ? SNP_PULL_GATHER : SNP_PULL_STAGED;
+  o->pull_mode = s->layout != SNP_LAYOUT_CSR_PULL ? 0
+                 : s->d.pull_wide ? SNP_PULL_WIDE
+                 : s->d.pull_gather ? SNP_PULL_GATHER : SNP_PULL_STAGED;
   o->push_mode = s->layout == SNP_LAYOUT_CSR_PULL ? 0 : s->d.push_binned ? SNP_PUSH_BINNED : SNP_PUSH_ATOMIC;
   o->reserved = 0;
   o->device_bytes = s->device_bytes;

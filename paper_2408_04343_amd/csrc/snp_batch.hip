@@ -99,7 +99,9 @@ int upload_tables(snp_batch* b) {
   int32_t tiles[2] = {0, 0};
   size_t lds[2] = {0, 0};
   for (snp_sys* s : b->members) {
-    const int g = group_of(s->d);
+    if (s->d.layout == L_CSR_PULL && s->d.pull_wide)
+    return fail(SNP_ENOTSUP, "systems in the wide pull schedule run alone");
+  const int g = group_of(s->d);
     tiles[g] += (s->q + step_tile(s->d) - 1) / step_tile(s->d);
     if (s->d.layout == L_CSR_PULL) lds[g] = std::max(lds[g], pull_lds_bytes(s->d));
     else if (s->d.push_binned) lds[g] = std::max(lds[g], bin_lds_bytes(s->d));
@@ -185,6 +187,8 @@ int add_member(snp_batch* b, snp_sys* s) {
   if (!s) return fail(SNP_EINVAL, "null handle");
   if (s->in_batch) return fail(SNP_EBUSY, "handle already in a batch");
   if (s->dev != b->dev) return fail(SNP_EINVAL, "handle on another device");
+  if (s->d.layout == L_CSR_PULL && s->d.pull_wide)
+    return fail(SNP_ENOTSUP, "systems in the wide pull schedule run alone");
   const int g = group_of(s->d);
   const SysDev& any = b->has_proto[0] ? b->proto[0] : b->proto[1];
   if ((b->has_proto[0] || b->has_proto[1]) && !compatible(any, s->d))

@@ -102,6 +102,11 @@ struct SysDev {
   int32_t pull_nc;           // number of source chunks
   int32_t pull_tb;           // log2 of the neurons per block (tile)
   int32_t pull_gather;       // 1: read emitted values from device memory (no LDS chunk)
+  int32_t pull_wide;         // 1: wide schedule (reception and many-rule choices by waves)
+  int32_t* recv;             // wide: [q] spikes received at the step being executed
+  int32_t* hsel;             // wide: [q] rule slot chosen for a neuron with many rules
+  const int32_t* heavy;      // wide: [n_heavy] neurons with more than SEL_LIGHT_RULES rules
+  int32_t n_heavy;
   // bookkeeping
   Ctl* ctl;
   uint64_t* digests;         // ring [ring]
@@ -113,6 +118,7 @@ struct SysDev {
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull_gather(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_pull_wide(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull_batch_gather(const SysDev& s, const SysDev* members, const int2* tiles,
                                          const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                          hipStream_t st);

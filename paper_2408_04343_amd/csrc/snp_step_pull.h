@@ -11,6 +11,11 @@ namespace snp {
 
 constexpr int PULL_NPT = 4;              // neurons per thread
 
+// Reception modes of the pull kernel.  PM_WIDE: the in-edges were summed per
+// target by recv_wide_kernel into s.recv, and the rules of neurons with many
+// rules were chosen by sel_wide_kernel into s.hsel, before this kernel.
+constexpr int PM_STAGED = 0, PM_GATHER = 1, PM_WIDE = 2;
+
 // Each block owns 2^TB consecutive neurons (4 per thread).  Reception of step
 // k-1: the in-edges of the tile are stored per source chunk as u32 records
 // (source offset in the chunk << TB | target offset in the tile), each
@@ -22,7 +27,7 @@ constexpr int PULL_NPT = 4;              // neurons per thread
 // per neuron, and the block packs its neurons' emitted values into the emit
 // vector of step k.  Rule offsets and the first rule record of every neuron
 // are loaded before the reception so that their latency overlaps it.
-template <int TB, int W, int RB, uint32_t FLAGS, bool GATHER>
+template <int TB, int W, int RB, uint32_t FLAGS, int MODE>
 __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t j, uint32_t* lds,
                                           unsigned long long* red, int32_t* ndefer) {
   constexpr int PULL_TILE = 1 << TB;
@@ -57,7 +62,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   for (int w = tid; w < TILE_WORDS; w += PULL_NT) stage[w] = 0u;
   if (tid == 0) *ndefer = 0;
 
-  if (GATHER && k > 0) {
+  if (MODE == PM_GATHER && k > 0) {
     // GATHER: one pass over all in-edges of the tile; every edge reads its
     // source's word of the emit vector in device memory.  A thread's group
     // index only grows, so it follows the chunk boundaries with a cursor.
@@ -106,7 +111,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
         }
       }
     }
-  } else if (!GATHER && k > 0) {
+  } else if (MODE == PM_STAGED && k > 0) {
     // STAGED: chunk by chunk, the chunk's values are copied into LDS first
     const uint32_t* ebuf = pick(s.emit[0], s.emit[1], k - 1);
     const int32_t* seg = s.pseg + (size_t)tile * s.pull_nc;
@@ -185,7 +190,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     if (t >= s.q) continue;
     int32_t C = in[r].C;
     if (k > 0) {
-      const int32_t got = acc[lt];
+      const int32_t got = MODE == PM_WIDE ? s.recv[t] : acc[lt];
       if (in[r].meta & META_RECV) {
         const uint32_t sum = (uint32_t)C + (uint32_t)got;
         if ((int32_t)sum < 0) s.ctl->overflow = 1;
@@ -202,13 +207,17 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     if (DIG && k > 0)
       dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
     if (defer_select<RB>(s, in[r])) {
+      if (MODE == PM_WIDE) {
+        emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt, s.hsel[t]));
+        continue;
+      }
       acc[lt] = C;  // the reception has been read: the slot carries the count to the wave
       defer[atomicAdd(ndefer, 1)] = (uint16_t)lt;
       continue;
     }
     emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt));
   }
-  if (s.sel_wave) {
+  if (MODE != PM_WIDE && s.sel_wave) {
     // neurons with many rules: a wave per neuron chooses, the owner applies
     __syncthreads();
     wave_select_pass<RB, PULL_NT>(s, t0, k, acc, defer, *ndefer);
@@ -238,16 +247,16 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   }
 }
 
-template <int TB, int W, int RB, uint32_t FLAGS, bool GATHER>
+template <int TB, int W, int RB, uint32_t FLAGS, int MODE>
 __global__ void __launch_bounds__((1 << TB) / PULL_NPT) step_pull_kernel(SysDev s, int32_t j) {
   extern __shared__ uint4 lds4[];
   __shared__ unsigned long long red[(1 << TB) / PULL_NPT / 64];
   __shared__ int32_t ndefer;
-  pull_body<TB, W, RB, FLAGS, GATHER>(s, blockIdx.x, j, (uint32_t*)lds4, red, &ndefer);
+  pull_body<TB, W, RB, FLAGS, MODE>(s, blockIdx.x, j, (uint32_t*)lds4, red, &ndefer);
 }
 
 // Batched form: block b runs tile tiles[b].y of system members[tiles[b].x].
-template <int TB, int W, int RB, uint32_t FLAGS, bool GATHER>
+template <int TB, int W, int RB, uint32_t FLAGS, int MODE>
 __global__ void __launch_bounds__((1 << TB) / PULL_NPT)
     step_pull_batch_kernel(const SysDev* __restrict__ members, const int2* __restrict__ tiles,
                            const int32_t* __restrict__ ntiles, int32_t j) {
@@ -257,12 +266,12 @@ __global__ void __launch_bounds__((1 << TB) / PULL_NPT)
   if ((int32_t)blockIdx.x >= *ntiles) return;
   const int2 tm = tiles[blockIdx.x];
   const SysDev s = members[tm.x];
-  pull_body<TB, W, RB, FLAGS, GATHER>(s, tm.y, j, (uint32_t*)lds4, red, &ndefer);
+  pull_body<TB, W, RB, FLAGS, MODE>(s, tm.y, j, (uint32_t*)lds4, red, &ndefer);
 }
 
 
-// Host launchers of one reception mode: TB = tile bits, G = gather.
-template <int TB, bool G, int RB, uint32_t FL>
+// Host launchers of one reception mode: TB = tile bits, G = PM_*.
+template <int TB, int G, int RB, uint32_t FL>
 static hipError_t launch_pull_rf(const SysDev& s, int32_t j, hipStream_t st) {
   const int tile = 1 << TB, nt = tile / PULL_NPT;
   const dim3 grid((s.q + tile - 1) / tile);
@@ -279,7 +288,7 @@ static hipError_t launch_pull_rf(const SysDev& s, int32_t j, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int TB, bool G, int RB, uint32_t FL>
+template <int TB, int G, int RB, uint32_t FL>
 static hipError_t launch_pull_batch_rf(const SysDev& s, const SysDev* members, const int2* tiles,
                                        const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                        hipStream_t st) {
@@ -304,7 +313,7 @@ static hipError_t launch_pull_batch_rf(const SysDev& s, const SysDev* members, c
     default: return FN<TB, G, RB, F_DIGEST | F_COUNTERS>(__VA_ARGS__);     \
   }
 
-template <int TB, bool G>
+template <int TB, int G>
 static hipError_t launch_pull_mode(const SysDev& s, int32_t j, hipStream_t st) {
   if (s.rule_bytes == 8) {
     SNP_FLAGS_DISPATCH(launch_pull_rf, 8, s, j, st)
@@ -312,7 +321,7 @@ static hipError_t launch_pull_mode(const SysDev& s, int32_t j, hipStream_t st) {
   SNP_FLAGS_DISPATCH(launch_pull_rf, 16, s, j, st)
 }
 
-template <int TB, bool G>
+template <int TB, int G>
 static hipError_t launch_pull_batch_mode(const SysDev& s, const SysDev* members, const int2* tiles,
                                          const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                          hipStream_t st) {

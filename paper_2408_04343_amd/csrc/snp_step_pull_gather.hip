@@ -6,13 +6,13 @@
 namespace snp {
 
 hipError_t launch_step_pull_gather(const SysDev& s, int32_t j, hipStream_t st) {
-  return launch_pull_mode<PULL_TB_GATHER, true>(s, j, st);
+  return launch_pull_mode<PULL_TB_GATHER, PM_GATHER>(s, j, st);
 }
 
 hipError_t launch_step_pull_batch_gather(const SysDev& s, const SysDev* members, const int2* tiles,
                                          const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                          hipStream_t st) {
-  return launch_pull_batch_mode<PULL_TB_GATHER, true>(s, members, tiles, ntiles, grid, lds, j, st);
+  return launch_pull_batch_mode<PULL_TB_GATHER, PM_GATHER>(s, members, tiles, ntiles, grid, lds, j, st);
 }
 
 }  // namespace snp

@@ -227,37 +227,34 @@ def sort_system(values) -> SnpSpec:
     o_j..o_n and forgets a^x for every other x in 1..n (firing rule first,
     then the forgetting rules; at n = 3 in exactly the order of Table 1,
     otherwise for x = n..1).  q = 3n, m = n + n^2, maximum out-degree n."""
-    v = [int(x) for x in values]
-    n = len(v)
+    v = np.asarray([int(x) for x in values], np.int64)
+    n = int(v.size)
     q = 3 * n
-    I = list(range(0, n))
-    S = list(range(n, 2 * n))
-    O = list(range(2 * n, 3 * n))
-    rules = []
-    for j in range(n):
-        rules.append((I[j], 1, 1, 1, 1, 0))                 # a+/a -> a
-    for j in range(n):
-        fire = n - j
-        rules.append((S[j], fire, 0, fire, 1, 0))           # a^(n-j+1) -> a
-        if n == 3:
-            forget = _TABLE1_FORGET_ORDER[j]                # rule order of Table 1
-        else:
-            forget = [x for x in range(n, 0, -1) if x != fire]
-        for x in forget:
-            rules.append((S[j], x, 0, x, 0, 0))             # a^x -> lambda
-    src, dst = [], []
-    for j in range(n):
-        for l in range(n):
-            src.append(I[j]); dst.append(S[l])
-    for j in range(n):
-        for l in range(j, n):
-            src.append(S[j]); dst.append(O[l])
+    I = np.arange(0, n, dtype=np.int64)
+    S = np.arange(n, 2 * n, dtype=np.int64)
+    O = np.arange(2 * n, 3 * n, dtype=np.int64)
+    ones, zeros = np.ones(n, np.int64), np.zeros(n, np.int64)
+    r_in = np.stack([I, ones, ones, ones, ones, zeros], axis=1)            # a+/a -> a
+    fire = n - np.arange(n, dtype=np.int64)                                # a^(n-j+1) -> a
+    if n == 3:
+        forget = np.array(_TABLE1_FORGET_ORDER, np.int64)                  # rule order of Table 1
+    else:
+        xs = np.arange(n, 0, -1, dtype=np.int64)                           # x = n..1; x = fire at j
+        keep = ~np.eye(n, dtype=bool)
+        forget = np.broadcast_to(xs, (n, n))[keep].reshape(n, n - 1)
+    base = np.concatenate([fire[:, None], forget.reshape(n, -1)], axis=1)  # [n, n]
+    per_row = base.shape[1]
+    r_s = np.stack([np.repeat(S, per_row), base.ravel(), np.zeros(n * per_row, np.int64), base.ravel(),
+                    np.tile(np.r_[1, np.zeros(per_row - 1, np.int64)], n),
+                    np.zeros(n * per_row, np.int64)], axis=1)
+    rules = np.concatenate([r_in, r_s]).astype(np.int32)
+    jj, ll = np.triu_indices(n)
+    # already in (src, dst) order: inputs before sorting neurons, targets ascending
+    src = np.concatenate([np.repeat(I, n), S[jj]]).astype(np.int32)
+    dst = np.concatenate([np.tile(S, n), O[ll]]).astype(np.int32)
     spikes0 = np.zeros(q, np.int32)
     spikes0[:n] = v
-    order = np.lexsort((np.array(dst), np.array(src)))
-    return SnpSpec("sort%d" % n, q, spikes0, np.array(rules, np.int32),
-                   np.array(src, np.int32)[order], np.array(dst, np.int32)[order],
-                   SELECT_FIRST, 0, max(v) + 2 if v else 1)
+    return SnpSpec("sort%d" % n, q, spikes0, rules, src, dst, SELECT_FIRST, 0, int(v.max()) + 2 if n else 1)
 
 
 def small_random(seed: int, q: int, max_deg: int = 4, max_rules: int = 3, dmax: int = 2,

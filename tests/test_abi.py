@@ -56,7 +56,7 @@ def test_footprint_orders():
     dict(rules=[(0, -1, 0, 1, 1, 0)]),
     dict(rules=[(0, 1, 0, 1, 1, -1)]),
     dict(rules=[(2, 1, 0, 1, 1, 0)]),
-    dict(pull_mode=3),
+    dict(pull_mode=4),
     dict(pull_mode=-1),
 ])
 def test_invalid_systems_rejected_before_any_device_call(bad):

@@ -16,14 +16,14 @@ pytestmark = pytest.mark.gpu
 # emitted values from device memory (plain "csr_pull" stages them in LDS at
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
 # device-wide atomic adds
-LAYOUTS = ["csr_pull", "csr_pull_gather", "optimized", "sliced", "ell", "csr_push",
+LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "sliced", "ell", "csr_push",
            "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
 
 
 def lk(layout):
     """System keyword arguments of a test layout name."""
-    if layout == "csr_pull_gather":
-        return {"layout": "csr_pull", "pull_mode": "gather"}
+    if layout in ("csr_pull_gather", "csr_pull_wide"):
+        return {"layout": "csr_pull", "pull_mode": layout[len("csr_pull_"):]}
     if layout.endswith("_atomic"):
         return {"layout": layout[:-len("_atomic")], "push_mode": "atomic"}
     return {"layout": layout}
@@ -120,13 +120,16 @@ def test_sort_family_closed_form(binding, layout):
         g.close()
 
 
-@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "sliced", "ell"])
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_pull_staged", "sliced", "ell"])
 def test_sort_family_many_rules(binding, layout):
     # 700 rules on each sorting neuron: a wave scans them 64 at a time
     rng = np.random.default_rng(12)
     v = rng.integers(1, 400, size=700).tolist()
     spec = wl.sort_system(v)
-    g = binding.System.from_spec(spec, **lk(layout))
+    kw = {"layout": "csr_pull", "pull_mode": "staged"} if layout == "csr_pull_staged" else lk(layout)
+    g = binding.System.from_spec(spec, **kw)
+    if layout == "csr_pull":   # 735 K in-edges on one 4096-neuron tile: the wide schedule
+        assert g.info()["pull_mode"] == binding.PULL_WIDE
     g.step(10_000)
     assert g.steps_done() == (max(v) + 1, True)
     C = g.read_config()
@@ -446,6 +449,14 @@ def test_batch_mixes_reception_modes(binding, layout, modes):
         assert g.steps_done()[0] == ref["steps"], sp.name
         assert np.array_equal(g.read_digests(0, ref["steps"]), ref["digests"]), sp.name
     b.close()
+
+
+def test_batch_rejects_wide_members(binding):
+    a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", pull_mode="wide")
+    with pytest.raises(binding.SnpError) as ei:
+        binding.Batch([a])
+    assert ei.value.status == -6
+    a.step(3)
 
 
 def test_batch_rejects_mixed_members(binding):
