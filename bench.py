@@ -108,54 +108,78 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
         sizes = np.maximum(1000, (sizes * scale).astype(np.int64))
     specs = [wl.config4_system(j, int(sizes[j]), 4, steps) for j in range(n)]
     gen_s = time.time() - t0
+    # the tuner's choice on the smallest, the median and the largest member
+    from paper_2408_04343_amd import tune
+    order = np.argsort(sizes)
+    tuned = {}
+    for j in (order[0], order[n // 2], order[-1]):
+        ch = tune.tune(specs[j], layout="csr_pull", steps=64, emit_bits=2)
+        tuned[int(sizes[j])] = {"choice": ch.mode, "auto": ch.auto,
+                                "us_per_step": {k: round(v, 2) for k, v in ch.us_per_step.items()}}
+        log("tuner, member of %d neurons: %s (auto %s) %s" % (sizes[j], ch.mode, ch.auto, ch.us_per_step))
     stream = torch.cuda.Stream()
-    t0 = time.time()
-    systems = [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2,
-                                        stream=stream.cuda_stream) for sp in specs]
-    create_s = time.time() - t0
     total_q = int(sum(sp.q for sp in specs))
-    # plain: each system alone, one after another on one stream
-    for g in systems:
-        g.step(warmup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for g in systems:
-        g.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1)
-    plain_digest = [g.digest() for g in systems]
-    # batched: back to the initial states, one launch per step for all systems
-    for sp, g in zip(specs, systems):
-        g.write_state(sp.spikes0, np.zeros(sp.q, np.int32), None, None, 0)
-    b = binding.Batch(systems, chunk=chunk, capacity_members=n,
-                      capacity_tiles=sum((sp.q + 4095) // 4096 for sp in specs))
-    b.step(warmup)
-    b.sync()
-    bs = b.stream if b.stream is not None else stream
-    e0.record(bs)
-    b.step(steps)
-    e1.record(bs)
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1)
-    members, done_steps, _ = b.status()
-    ntiles = b.size()[1]
-    b.close()
-    same = all(g.digest() == d for g, d in zip(systems, plain_digest))
-    for g in systems:
-        g.close()
     nu = total_q * steps
-    log("batched %d systems (%d neurons, %d tiles): %.2f ms vs plain sequential %.2f ms" %
-        (n, total_q, ntiles, batch_ms, plain_ms))
+    modes = {}
+    plain_ms = plain_digest = None
+    create_s = 0.0
+    for mode in ("auto", "staged", "gather"):
+        t0 = time.time()
+        systems = [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2, pull_mode=mode,
+                                            stream=stream.cuda_stream) for sp in specs]
+        if mode == "auto":
+            create_s = time.time() - t0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if plain_ms is None:
+            # plain: each system alone, one after another on one stream
+            for g in systems:
+                g.step(warmup)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for g in systems:
+                g.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            plain_ms = e0.elapsed_time(e1)
+            plain_digest = [g.digest() for g in systems]
+            # back to the initial states for the batched run
+            for sp, g in zip(specs, systems):
+                g.write_state(sp.spikes0, np.zeros(sp.q, np.int32), None, None, 0)
+        # batched: one launch per step and reception mode for all systems
+        b = binding.Batch(systems, chunk=chunk, capacity_members=n,
+                          capacity_tiles=sum((sp.q + 1023) // 1024 for sp in specs))
+        b.step(warmup)
+        b.sync()
+        bs = b.stream if b.stream is not None else stream
+        e0.record(bs)
+        b.step(steps)
+        e1.record(bs)
+        torch.cuda.synchronize()
+        batch_ms = e0.elapsed_time(e1)
+        ntiles = b.size()[1]
+        b.close()
+        same = all(g.digest() == d for g, d in zip(systems, plain_digest))
+        ngather = sum(1 for g in systems if g.info()["pull_mode"] == binding.PULL_GATHER)
+        for g in systems:
+            g.close()
+        modes[mode] = {"ms": batch_ms, "neuron_updates_per_s": nu / (batch_ms * 1e-3), "tiles": ntiles,
+                       "gather_members": ngather, "equals_plain": bool(same)}
+        log("batched %d systems (%d neurons, %s: %d gather members, %d tiles): %.2f ms vs plain sequential "
+            "%.2f ms, digests %s" % (n, total_q, mode, ngather, ntiles, batch_ms, plain_ms,
+                                     "equal" if same else "DIFFERENT"))
+    best = min(modes, key=lambda m: modes[m]["ms"])
     return {"workload": "config4-batched: %d systems, sizes log-uniform 1,000-262,144 (total %d "
                         "neurons), Poisson(12) out-degree, 1-4 rules, delays 0..3, hash choice, "
                         "%d timed steps" % (n, total_q, steps),
-            "systems": n, "neurons": total_q, "steps": steps, "tiles": ntiles,
-            "batched": {"ms": batch_ms, "neuron_updates_per_s": nu / (batch_ms * 1e-3)},
+            "systems": n, "neurons": total_q, "steps": steps, "tiles": modes["auto"]["tiles"],
+            "batched": {"ms": modes["auto"]["ms"], "neuron_updates_per_s": modes["auto"]["neuron_updates_per_s"]},
+            "batched_by_mode": modes, "fastest_mode": best,
             "plain_sequential": {"ms": plain_ms, "neuron_updates_per_s": nu / (plain_ms * 1e-3)},
-            "speedup": plain_ms / batch_ms, "batched_equals_plain": bool(same),
-            "gen_s": round(gen_s, 1), "create_s": round(create_s, 1)}
+            "speedup": plain_ms / modes["auto"]["ms"],
+            "batched_equals_plain": all(m["equals_plain"] for m in modes.values()),
+            "gen_s": round(gen_s, 1), "create_s": round(create_s, 1),
+            "tuner": {"note": "measured schedule choice (graph of 64 steps per candidate) on the "
+                              "smallest, median and largest member, each alone", "members": tuned}}
 
 
 def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64):

@@ -68,9 +68,6 @@ int32_t pull_chunk_sources(int32_t w, int32_t tb) {
 // record encoding bounds it.
 int32_t pull_gather_chunk(int32_t tb) { return (int32_t)((1LL << (32 - tb)) - 128); }
 
-// AUTO: staging copies the whole emit vector into every block, gathering
-// costs one scattered load per in-edge; gather when a block's in-edges are
-// fewer than half the words of the emit vector.
 // AUTO: wide above 256 K in-edges per 4096-neuron tile (a block per tile
 // would stream them alone).
 bool pull_wide(int32_t mode, int32_t q, int64_t nsyn) {
@@ -79,11 +76,18 @@ bool pull_wide(int32_t mode, int32_t q, int64_t nsyn) {
   return nsyn / tiles > 262144;
 }
 
+// AUTO: staging copies the whole emit vector into every block, gathering
+// costs one scattered load per in-edge; gather when a block's in-edges are
+// fewer than half the words of the emit vector.  Gather also when the
+// staged tiles (one block of 1024 threads each) are fewer than the 256
+// compute units and the system has at least 8192 neurons (smaller ones are
+// bound by the launch, where the larger blocks do better).
 bool pull_gathers(int32_t mode, int32_t q, int64_t nsyn, int32_t w) {
   if (mode != SNP_PULL_AUTO) return mode == SNP_PULL_GATHER;
   const int64_t tiles = ((int64_t)q + (1LL << PULL_TB_STAGED) - 1) >> PULL_TB_STAGED;
+  const int64_t gtiles = ((int64_t)q + (1LL << PULL_TB_GATHER) - 1) >> PULL_TB_GATHER;
   const int64_t words = ((int64_t)q * w + 31) / 32;
-  return 2 * (nsyn / tiles) < words;
+  return 2 * (nsyn / tiles) < words || (tiles < 256 && gtiles > tiles && q >= 8192);
 }
 
 struct Plan {

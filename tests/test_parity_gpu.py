@@ -451,6 +451,21 @@ def test_batch_mixes_reception_modes(binding, layout, modes):
     b.close()
 
 
+@pytest.mark.parametrize("layout", ["csr_pull", "ell"])
+def test_tuner_times_every_schedule(binding, layout):
+    from paper_2408_04343_amd import tune
+    spec = wl.config2(q=50_000, steps=100)
+    ch = tune.tune(spec, layout=layout, steps=32)
+    expect = tune.PULL_CANDIDATES if layout == "csr_pull" else tune.PUSH_CANDIDATES
+    assert set(ch.us_per_step) == set(expect) and all(v > 0 for v in ch.us_per_step.values())
+    assert ch.mode == min(ch.us_per_step, key=ch.us_per_step.get) and ch.auto in expect
+    # the chosen schedule computes the oracle's trajectory
+    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(20, want_state=False)
+    g = binding.System.from_spec(spec, digest=True, **ch.kwargs())
+    g.step(20)
+    assert np.array_equal(g.read_digests(0, 20), ref["digests"])
+
+
 def test_batch_rejects_wide_members(binding):
     a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", pull_mode="wide")
     with pytest.raises(binding.SnpError) as ei:
