@@ -246,6 +246,16 @@ int snp_read_counters(snp_sys* sys, snp_counters* out, int64_t first, int64_t co
 int snp_write_state(snp_sys* sys, const int32_t* config, const int32_t* delays,
                     const int32_t* pending, const int32_t* spiking, int64_t k);
 
+/* Synapse plasticity between steps (Sec. 7 names it as the variant that
+ * suits the compressed layouts): replaces the synapse set of the system.
+ * The state (C_k with every spike sent so far received, D_k, pending rules,
+ * S_{k-1}, k) is kept; spikes sent from step k on travel along the new set.
+ * The representation is rebuilt with the options of snp_create (AUTO modes
+ * decide again); digest and counter rings restart.  Same validation as
+ * snp_create (SNP_EINVAL; the system is then unchanged).  SNP_EBUSY for a
+ * handle in a batch or sharing its representation with clones.            */
+int snp_set_synapses(snp_sys* sys, int64_t nsyn, const int32_t* syn_src, const int32_t* syn_dst);
+
 /* Device copy of the representation, for inspection (host buffers):
  *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
  *   which = SNP_LAYOUT_SLICED: the slices expanded to the same [z][q] Sy;

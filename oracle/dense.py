@@ -102,6 +102,13 @@ class DenseSystem:
         self.k = 0
         self.owner = self.rules[:, 0] if self.m else np.zeros(0, np.int64)
 
+    def set_synapses(self, syn):
+        """Synapse plasticity between steps: the matrix is rebuilt from the
+        new synapse set (Sec. 7), the state is kept."""
+        self.M = transition_matrix(self.q, self.rules, syn)
+        self.Mp = production_matrix(self.q, self.rules, syn)
+        self.Mc = self.M - self.Mp
+
     def halted(self):
         if np.any(self.D != 0):
             return False

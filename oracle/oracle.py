@@ -99,6 +99,8 @@ def _load():
         lib.orc_max_outdeg.restype = ct.c_int32
         lib.orc_build_ell.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32), P(ct.c_int32)]
         lib.orc_build_sy.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
+        lib.orc_set_synapses.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32)]
+        lib.orc_set_synapses.restype = ct.c_int
         _lib = lib
     return _lib
 
@@ -171,6 +173,14 @@ class OracleSystem:
 
     def step(self, n: int) -> int:
         return int(self._lib.orc_step(self._h, n))
+
+    def set_synapses(self, src, dst):
+        """Replaces the synapse set between steps (state kept)."""
+        sa = np.ascontiguousarray(src, np.int32)
+        da = np.ascontiguousarray(dst, np.int32)
+        st = self._lib.orc_set_synapses(self._h, len(sa), _ip(sa), _ip(da))
+        if st != 0:
+            raise OracleError("orc_set_synapses failed with %d" % st)
 
     def step_record(self, n: int, want_state=True):
         """Runs up to n steps; returns dict of per-step C, D, S [t, q], digests [t], counters."""

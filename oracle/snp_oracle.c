@@ -231,6 +231,53 @@ int orc_create(int32_t q, const int32_t* spikes0, int32_t m, const orc_rule* rul
   return 0;
 }
 
+/* Synapse plasticity (Sec. 7 names it as the variant that suits the
+ * compressed layouts): between two steps the synapse set is replaced; the
+ * state (C, D, pending rules, step count) is kept.  Every spike sent so far
+ * has already been received (the two phases of a step complete it), so the
+ * new set only carries spikes sent from the next step on.  Same validation
+ * as orc_create; on error the system is unchanged. */
+int orc_set_synapses(orc_sys* s, int64_t nsyn, const int32_t* src, const int32_t* dst) {
+  const int32_t q = s->q;
+  if (nsyn < 0) return -1;
+  for (int64_t e = 0; e < nsyn; ++e) {
+    if (src[e] < 0 || src[e] >= q || dst[e] < 0 || dst[e] >= q) return -1;
+    if (src[e] == dst[e]) return -1;
+  }
+  int32_t* ostart = (int32_t*)calloc((size_t)q + 1, sizeof(int32_t));
+  int32_t* olist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nsyn > 0 ? nsyn : 1));
+  int32_t* indeg = (int32_t*)calloc((size_t)q, sizeof(int32_t));
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)q);
+  if (!ostart || !olist || !indeg || !fill) {
+    free(ostart); free(olist); free(indeg); free(fill);
+    return -2;
+  }
+  for (int64_t e = 0; e < nsyn; ++e) {
+    ostart[src[e] + 1]++;
+    indeg[dst[e]]++;
+  }
+  for (int32_t i = 0; i < q; ++i) ostart[i + 1] += ostart[i];
+  for (int32_t i = 0; i < q; ++i) fill[i] = ostart[i];
+  for (int64_t e = 0; e < nsyn; ++e) olist[fill[src[e]]++] = dst[e];
+  /* syn is a set: a repeated pair is invalid (fill doubles as the stamp) */
+  for (int32_t i = 0; i < q; ++i) fill[i] = -1;
+  for (int32_t i = 0; i < q; ++i)
+    for (int32_t e = ostart[i]; e < ostart[i + 1]; ++e) {
+      if (fill[olist[e]] == i) {
+        free(ostart); free(olist); free(indeg); free(fill);
+        return -1;
+      }
+      fill[olist[e]] = i;
+    }
+  free(fill);
+  free(s->ostart); free(s->olist); free(s->indeg);
+  s->ostart = ostart;
+  s->olist = olist;
+  s->indeg = indeg;
+  s->nsyn = nsyn;
+  return 0;
+}
+
 void orc_destroy(orc_sys* s) {
   if (!s) return;
   free(s->rules); free(s->rstart); free(s->rlist); free(s->ostart); free(s->olist);

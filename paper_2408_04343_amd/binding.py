@@ -38,7 +38,7 @@ SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_
            "snp_strerror", "snp_last_error", "snp_set_step_limit", "snp_batch_opts_default",
            "snp_batch_create", "snp_batch_add", "snp_batch_remove", "snp_batch_step",
            "snp_batch_sync", "snp_batch_size", "snp_batch_members", "snp_batch_status",
-           "snp_batch_destroy", "snp_clone"]
+           "snp_batch_destroy", "snp_clone", "snp_set_synapses"]
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
@@ -127,6 +127,7 @@ def _load():
         "snp_batch_status": (ct.c_int, [vp, i64p, i32p]),
         "snp_batch_destroy": (ct.c_int, [vp]),
         "snp_clone": (ct.c_int, [vp, i32p, ct.c_uint64, vp, P(vp)]),
+        "snp_set_synapses": (ct.c_int, [vp, ct.c_int64, i32p, i32p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -332,6 +333,13 @@ class System:
         S = _i32(spiking) if spiking is not None else None
         _check(lib.snp_write_state(self._h, _ptr(C), _ptr(D), _ptr(P) if P is not None else None,
                                    _ptr(S) if S is not None else None, int(k)))
+
+    def set_synapses(self, src, dst):
+        """Replaces the synapse set between steps; the state is kept."""
+        sa, da = _i32(src), _i32(dst)
+        if sa.shape != da.shape:
+            raise ValueError("src and dst must have the same length")
+        _check(lib.snp_set_synapses(self._h, len(sa), _ptr(sa), _ptr(da)))
 
     def read_layout(self, which):
         which = LAYOUTS[which] if isinstance(which, str) else int(which)

@@ -425,6 +425,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   s->layout = o.layout;
   s->chunk = o.chunk;
   s->h_spikes0.assign(spikes0, spikes0 + q);
+  if (m > 0) s->h_rules.assign(rules, rules + m);
 
   auto bail = [&](int st) {
     s->release();
@@ -955,6 +956,37 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
   if (s->d.flags & F_COUNTERS)
     HIPCHK(hipMemsetAsync(s->d.counters, 0, 8 * NCOUNT * (size_t)(s->d.ring + 1), s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  return SNP_OK;
+}
+
+int snp_set_synapses(snp_sys* s, int64_t nsyn, const int32_t* syn_src, const int32_t* syn_dst) {
+  if (!s || nsyn < 0 || (nsyn > 0 && (!syn_src || !syn_dst))) return fail(SNP_EINVAL, "bad argument");
+  if (s->in_batch) return fail(SNP_EBUSY, "handle is in a batch");
+  if (s->base || s->clones) return fail(SNP_EBUSY, "the representation is shared with clones");
+  DevScope ds(s->dev);
+  const int32_t q = s->q;
+  // state k with every spike sent so far received
+  StateInfo si;
+  TRY(query(s, &si));
+  TRY(materialize(s, &si));
+  if (si.overflow) return fail(SNP_EOVERFLOW, "a spike count left the int32 range");
+  std::vector<int32_t> st4((size_t)4 * q);
+  HIPCHK(hipMemcpyAsync(st4.data(), s->scratch, 16 * (size_t)q, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const int32_t *C = st4.data(), *D = C + q, *S = C + 2 * (size_t)q, *P = C + 3 * (size_t)q;
+  // the same rules and options over the new synapse set; on error the
+  // handle is untouched
+  snp_sys* n = nullptr;
+  int st = snp_create(q, C, s->m, s->h_rules.data(), nsyn, syn_src, syn_dst, &s->opts, &n);
+  if (st != SNP_OK) return st;
+  st = snp_write_state(n, C, D, P, S, si.steps);
+  if (st != SNP_OK) {
+    snp_destroy(n);
+    return st;
+  }
+  // the caller's handle takes the new representation; the old one goes
+  std::swap(*s, *n);
+  snp_destroy(n);
   return SNP_OK;
 }
 

@@ -53,6 +53,7 @@ struct snp_sys {
   snp_sys* base = nullptr;              // clones: the handle whose structure they share
   int clones = 0;                       // live clones sharing this handle's structure
   std::vector<int32_t> h_spikes0;       // C_0, for clones without their own
+  std::vector<snp_rule> h_rules;        // the caller's rules, to rebuild on new synapses
   snp::Ctl ctl_init{};                  // host copy of the initial control block
 
   void* dalloc(size_t bytes) {

@@ -258,6 +258,64 @@ def test_brute_force_against_dense_matrix(sem, sel):
     assert n > 300
 
 
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_synapse_plasticity_against_dense_matrix(sem):
+    # the synapse set changes after a few steps: the oracle's adjacency
+    # rebuild equals the transition matrix rebuilt from the new set, step by
+    # step (Sec. 7's plasticity, Sec. 2's C' = C + S M with the new M)
+    rng = np.random.default_rng(8)
+    for t in range(60):
+        spec = wl.small_random(2000 + t, 5, max_deg=3, max_rules=3, dmax=2, c0max=4, select=wl.SELECT_HASH)
+        other = wl.small_random(3000 + t, 5, max_deg=3, max_rules=1)
+        at = int(rng.integers(0, 4))
+        o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, sem, HASH, 5)
+        d = dense.DenseSystem(spec.q, spec.spikes0, spec.rules, list(zip(spec.src, spec.dst)), sem, HASH, 5)
+        for k in range(10):
+            if k == at:
+                o.set_synapses(other.src, other.dst)
+                d.set_synapses(list(zip(other.src, other.dst)))
+            o.step(1)
+            moved = d.step()
+            r = o.read()
+            assert r["C"].tolist() == d.C.tolist() and r["D"].tolist() == d.D.tolist(), (t, k)
+            if not moved:
+                break
+
+
+def test_synapse_plasticity_special_cases():
+    spec = wl.small_random(9, 400, max_deg=5, max_rules=3, dmax=2, c0max=6, select=wl.SELECT_HASH)
+    mk = lambda: orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, STD, HASH, 3)
+    # the same set again changes nothing
+    a, b = mk(), mk()
+    a.step(7)
+    b.step(7)
+    b.set_synapses(spec.src, spec.dst)
+    a.step(20)
+    b.step(20)
+    assert a.digest() == b.digest()
+    # no synapses left: from then on the system is the synapse-free system
+    # started from the state it had (no delays and FIRST, so nothing but the
+    # counts carries over)
+    nd = wl.small_random(10, 400, max_deg=5, max_rules=3, dmax=0, c0max=6)
+    c = orc.OracleSystem(nd.q, nd.spikes0, nd.rules, nd.src, nd.dst, STD, FIRST, 0)
+    c.step(5)
+    c.set_synapses([], [])
+    alone = orc.OracleSystem(nd.q, c.read()["C"], nd.rules, [], [], STD, FIRST, 0)
+    for k in range(12):
+        c.step(1)
+        alone.step(1)
+        assert c.read()["C"].tolist() == alone.read()["C"].tolist(), k
+    # invalid sets are rejected and leave the system unchanged
+    d = mk()
+    d.step(3)
+    before = d.digest()
+    with pytest.raises(orc.OracleError):
+        d.set_synapses([0, 0], [1, 1])        # repeated pair
+    with pytest.raises(orc.OracleError):
+        d.set_synapses([4], [4])              # self-loop
+    assert d.digest() == before
+
+
 def _valid_spiking_vectors(C, D, rules, q):
     """Every valid choice: each open neuron with an applicable rule picks one."""
     per = []

@@ -466,6 +466,58 @@ def test_tuner_times_every_schedule(binding, layout):
     assert np.array_equal(g.read_digests(0, 20), ref["digests"])
 
 
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_push"])
+def test_explore_samples_equal_their_keys_alone(binding, layout):
+    # one system, twelve HASH keys advanced together: every sample is the
+    # oracle's run with its key, and the keys do take different branches
+    from paper_2408_04343_amd import explore
+    spec = wl.small_random(41, 3000, max_deg=6, max_rules=4, dmax=2, c0max=8, select=wl.SELECT_HASH)
+    base = binding.System.from_spec(spec, layout=layout)
+    seeds = [wl.system_seed(77, x) for x in range(12)]
+    res = explore.explore(base, seeds, 30)
+    for x, sd in enumerate(seeds):
+        o = oracle_of(spec, orc.SEM_STANDARD, seed=sd)
+        o.step(30)
+        r = o.read()
+        assert res["steps"][x] == o.steps_done and bool(res["halted"][x]) == o.halted
+        assert np.array_equal(res["C"][x], r["C"]) and np.array_equal(res["D"][x], r["D"]), x
+    assert len(set(res["digest"].tolist())) > 1
+    base.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_synapse_plasticity_every_step(binding, layout):
+    # the synapse set is replaced after 7 steps (delays and pending rules in
+    # flight): every later step equals the oracle with the same change
+    spec = wl.small_random(51, 3000, max_deg=8, max_rules=4, dmax=3, c0max=8, select=wl.SELECT_HASH)
+    other = wl.small_random(52, 3000, max_deg=12, max_rules=1)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    g = binding.System.from_spec(spec, **lk(layout))
+    o.step(7)
+    g.step(7)
+    o.set_synapses(other.src, other.dst)
+    g.set_synapses(other.src, other.dst)
+    for t in range(15):
+        o.step(1)
+        g.step(1)
+        r = o.read()
+        assert np.array_equal(g.read_config(), r["C"]), (layout, t)
+        assert np.array_equal(g.read_delays(), r["D"]) and np.array_equal(g.read_spiking(), r["S"]), (layout, t)
+    assert g.steps_done()[0] == o.steps_done
+    # invalid sets are rejected and leave the system as it was
+    before = g.digest()
+    with pytest.raises(binding.SnpError) as ei:
+        g.set_synapses([0, 0], [1, 1])
+    assert ei.value.status == -1 and g.digest() == before
+    # shared or batched handles refuse
+    c = g.clone(seed=3)
+    with pytest.raises(binding.SnpError) as ei:
+        g.set_synapses(other.src, other.dst)
+    assert ei.value.status == -5
+    c.close()
+    g.close()
+
+
 def test_batch_rejects_wide_members(binding):
     a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", pull_mode="wide")
     with pytest.raises(binding.SnpError) as ei:
