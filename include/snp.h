@@ -118,6 +118,11 @@ extern "C" {
 #define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
 #define SNP_F_NO_GRAPH 0x4u /* launch step kernels one by one (no hipGraph)  */
 #define SNP_F_WIDE_RULES 0x8u /* keep 16-byte rule records even when 8 fit  */
+#define SNP_F_ELL_ROWS 0x10u  /* ELL stored row by row as Table 2 is drawn
+                                 ([z'][m]: a row contiguous over rules) instead
+                                 of rule by rule ([m][z']: a rule's column
+                                 contiguous, the default: only the columns of
+                                 emitting rules are read at a step)          */
 
 /* Device memory hooks (e.g. a framework's caching allocator).  `stream` is
  * the handle's hipStream_t.  NULL hooks = hipMalloc / hipFree.            */

@@ -150,7 +150,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
       p.add(8 * (ns + 1));
       p.add(4 * std::min<int64_t>((int64_t)z * ns * SLICE, (int64_t)SLICE * nnz));
     }
-    if (layout == L_ELL) p.add(8LL * (z + 1) * std::max(m, 1));
+    if (layout == L_ELL) p.add(8LL * ((z + 2) & ~1) * std::max(m, 1));
   }
   return p.bytes;
 }
@@ -544,6 +544,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   d.sel = o.select;
   d.sem = o.semantics;
   d.flags = o.flags & (SNP_F_DIGEST | SNP_F_COUNTERS);
+  d.ell_rows = (o.flags & SNP_F_ELL_ROWS) ? 1 : 0;
   d.seed = o.seed;
   d.ring = o.ring;
   d.emit_w = emit_width(pmax_all);
@@ -716,8 +717,11 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       d.sy = sy;
       if (hipSuccess != launch_build_sy(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy"));
     } else if (o.layout == SNP_LAYOUT_ELL) {
-      int2* ell = (int2*)s->dalloc(8 * (size_t)(z + 1) * (size_t)std::max(m, 1));
-      if (!ell) return bail(fail(SNP_ENOMEM, "ELL does not fit in device memory"));
+      // rule by rule, every column padded to an even number of pairs with nulls
+      const size_t rows = d.ell_rows ? (size_t)(z + 1) : (size_t)((z + 2) & ~1);
+      int2* ell = nullptr;
+      if ((st = alloc_fill(s, (void**)&ell, 8 * rows * (size_t)std::max(m, 1), 0xFF)) != SNP_OK)
+        return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "ELL does not fit in device memory") : st);
       d.ell = ell;
       if (hipSuccess != launch_build_ell(d, ell, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
     }
@@ -1021,11 +1025,13 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
     }
   } else if (which == SNP_LAYOUT_ELL) {
     if (!s->d.ell) return fail(SNP_EINVAL, "handle does not use the ELL layout");
-    std::vector<int32_t> tmp((size_t)need);
-    HIPCHK(hipMemcpy(tmp.data(), s->d.ell, 4 * (size_t)need, hipMemcpyDeviceToHost));
+    const size_t dev = 2 * (size_t)(s->d.ell_rows ? z + 1 : (z + 2) & ~1) * (size_t)std::max(m, 1);
+    std::vector<int32_t> tmp(dev);
+    HIPCHK(hipMemcpy(tmp.data(), s->d.ell, 4 * dev, hipMemcpyDeviceToHost));
     for (int64_t row = 0; row <= z; ++row)
       for (int32_t sl = 0; sl < m; ++sl) {
-        const int64_t src = (row * m + sl) * 2, dst = (row * m + (s->base ? s->base : s)->h_rid[sl]) * 2;
+        const int64_t src = ell_index(s->d, sl, (int32_t)row) * 2;
+        const int64_t dst = (row * m + (s->base ? s->base : s)->h_rid[sl]) * 2;
         out[dst] = tmp[(size_t)src];
         out[dst + 1] = tmp[(size_t)src + 1];
       }

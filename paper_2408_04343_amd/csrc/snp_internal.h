@@ -78,7 +78,9 @@ struct SysDev {
   const int32_t* sy;         // OPTIMIZED: [z][q] row-major, -1 = null; SLICED: the slices
   const int64_t* sy_off;     // SLICED: [q/64 + 1] first entry of each slice; slice b is
                              //   [h_b][64] row-major, h_b = (sy_off[b+1] - sy_off[b]) / 64
-  const int2* ell;           // ELL: [z+1][m] row-major (neuron, value), (-1, 0) = null
+  const int2* ell;           // ELL: (neuron, value) pairs, (-1, 0) = null; [m][z+1] (a rule's
+                             //   column contiguous) or, with ell_rows, [z+1][m]
+  int32_t ell_rows;
   const int32_t* out_ptr;    // CSR_PUSH: [q+1]
   const int32_t* out_col;    // CSR_PUSH: [nnz]
   const int32_t* out_deg;    // counters only: [q]
@@ -113,6 +115,12 @@ struct SysDev {
   unsigned long long* counters;  // ring [ring][NCOUNT]
   int64_t ring;
 };
+
+// Entry (rule slot, row) of the ELL matrix.
+__host__ __device__ inline int64_t ell_index(const SysDev& s, int32_t slot, int32_t row) {
+  // rule by rule: each column holds z + 1 pairs rounded up to an even count
+  return s.ell_rows ? (int64_t)row * s.m + slot : (int64_t)slot * ((s.z + 2) & ~1) + row;
+}
 
 // Host-side launchers (defined in snp_kernels.hip).
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st);

@@ -256,8 +256,8 @@ hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st) 
 }
 
 // ELL (Table 2): column of rule slot r of neuron i: row 0 = (i, -c), rows
-// 1..deg = (target, +p) for p > 0, the rest (-1, 0); stored row-major
-// [z+1][m] so that a row is contiguous over rules.
+// 1..deg = (target, +p) for p > 0, the rest (-1, 0); stored column by column
+// ([m][z+1]) or row by row ([z+1][m]), see ell_index.
 template <int RB>
 __global__ void build_ell_kernel(SysDev s, int2* ell) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,10 +265,10 @@ __global__ void build_ell_kernel(SysDev s, int2* ell) {
   const int32_t e0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - e0;
   for (int32_t r = s.rs[i]; r < s.rs[i + 1]; ++r) {
     const Rule rr = load_rule<RB>(s, r);
-    ell[r] = make_int2(i, -rr.c);
+    ell[ell_index(s, r, 0)] = make_int2(i, -rr.c);
     for (int32_t row = 1; row <= s.z; ++row) {
       const bool on = rr.p > 0 && row <= deg;
-      ell[(int64_t)row * s.m + r] = on ? make_int2(s.out_col[e0 + row - 1], rr.p) : make_int2(-1, 0);
+      ell[ell_index(s, r, row)] = on ? make_int2(s.out_col[e0 + row - 1], rr.p) : make_int2(-1, 0);
     }
   }
 }

@@ -136,8 +136,42 @@ __device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t ru
                                           int32_t jj) {
   if (LAYOUT == L_OPT) return make_int2(s.sy[(int64_t)jj * s.q + i], v);
   if (LAYOUT == L_SLICED) return make_int2(s.sy[e0 + (int64_t)jj * SLICE], v);
-  if (LAYOUT == L_ELL) return s.ell[(int64_t)(jj + 1) * s.m + rule];
+  if (LAYOUT == L_ELL) return s.ell[ell_index(s, rule, jj + 1)];
   return make_int2(s.out_col[e0 + jj], v);
+}
+
+// Entries jb .. jb + BIN_ROWS - 1 of the row of neuron i into x, target -1
+// at or past jend.  A column of the rule-by-rule ELL is contiguous and starts
+// 16-byte aligned (columns hold an even number of pairs), so its entries come
+// in 16-byte loads of two rows; the other layouts load entry by entry.
+template <int LAYOUT>
+__device__ __forceinline__ void bin_load(const SysDev& s, int32_t i, int32_t rule, int32_t v, int64_t e0,
+                                         int32_t jb, int32_t jend, int2* x) {
+  static_assert(BIN_ROWS == 8, "the ELL path loads 8 entries");
+  if (LAYOUT == L_ELL && !s.ell_rows) {
+    const int32_t zs = (s.z + 2) & ~1;
+    const int4* col = reinterpret_cast<const int4*>(s.ell + (int64_t)rule * zs);
+    // entry jj is row jj + 1: rows jb + 1 .. jb + 8 lie in pairs jb/2 .. jb/2 + 4
+    int4 pr[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int32_t p = (jb >> 1) + u;
+      pr[u] = 2 * p + 1 < zs ? col[p] : make_int4(-1, 0, -1, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int4 q = pr[(u + 1) >> 1];
+      x[u] = ((u + 1) & 1) ? make_int2(q.z, q.w) : make_int2(q.x, q.y);
+      if (jb + u >= jend) x[u].x = -1;
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < BIN_ROWS; ++u) {
+    // entries past the bound are clamped to the row's last entry and dropped
+    x[u] = bin_entry<LAYOUT>(s, i, rule, v, e0, min(jb + u, jend - 1));
+    if (jb + u >= jend) x[u].x = -1;
+  }
 }
 
 // Entries j0, j0 + stride, ... below jend of one row; stops at the null entry.
@@ -282,15 +316,14 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   {
     int2 x[BIN_NPT][BIN_ROWS];
 #pragma unroll
-    for (int r = 0; r < BIN_NPT; ++r)
+    for (int r = 0; r < BIN_NPT; ++r) {
+      if (jend[r] > 0) {
+        bin_load<LAYOUT>(s, t0 + tid + r * BIN_NT, rule[r], o[r].emit, e0[r], 0, jend[r], x[r]);
+      } else {
 #pragma unroll
-      for (int u = 0; u < BIN_ROWS; ++u) {
-        const int32_t i = t0 + tid + r * BIN_NT;
-        // rows past the bound are clamped to the row's last entry and dropped
-        const int32_t jj = min(u, jend[r] - 1);
-        x[r][u] = jend[r] > 0 ? bin_entry<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], jj) : make_int2(-1, 0);
-        if (u >= jend[r]) x[r][u].x = -1;
+        for (int u = 0; u < BIN_ROWS; ++u) x[r][u] = make_int2(-1, 0);
       }
+    }
 #pragma unroll
     for (int r = 0; r < BIN_NPT; ++r) {
       bool open = true;
@@ -310,11 +343,7 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     bool open = true;
     for (int32_t jb = BIN_ROWS; jb < lim && open; jb += BIN_ROWS) {
       int2 x[BIN_ROWS];
-#pragma unroll
-      for (int u = 0; u < BIN_ROWS; ++u) {
-        x[u] = bin_entry<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], min(jb + u, lim - 1));
-        if (jb + u >= lim) x[u].x = -1;
-      }
+      bin_load<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], jb, lim, x);
 #pragma unroll
       for (int u = 0; u < BIN_ROWS; ++u) {
         open = open && x[u].x >= 0;

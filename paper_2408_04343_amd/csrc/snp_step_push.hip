@@ -69,7 +69,7 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
       }
     } else if (LAYOUT == L_ELL) {
       for (int32_t r = 1; r <= s.z; ++r) {
-        const int2 pr = s.ell[(int64_t)r * s.m + o.erule];
+        const int2 pr = s.ell[ell_index(s, o.erule, r)];
         if (pr.x < 0) break;
         atomicAdd(&cur[pr.x], pr.y);
         ++deg;

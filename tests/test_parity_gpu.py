@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 # emitted values from device memory (plain "csr_pull" stages them in LDS at
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
 # device-wide atomic adds
-LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "sliced", "ell", "csr_push",
-           "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
+LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "sliced", "ell", "ell_rows",
+           "csr_push", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
 
 
 def lk(layout):
@@ -26,6 +26,8 @@ def lk(layout):
         return {"layout": "csr_pull", "pull_mode": layout[len("csr_pull_"):]}
     if layout.endswith("_atomic"):
         return {"layout": layout[:-len("_atomic")], "push_mode": "atomic"}
+    if layout == "ell_rows":   # ELL stored row by row (Table 2's drawing) instead of rule by rule
+        return {"layout": "ell", "ell_rows": True}
     return {"layout": layout}
 SEMS = [("standard", orc.SEM_STANDARD), ("paper_kernel", orc.SEM_PAPER_KERNEL)]
 
@@ -154,10 +156,11 @@ def test_layouts_built_on_device_match_tables(binding):
     assert sy.tolist() == int_matrix("table3_sort3_sy.txt")
     g = binding.System.from_spec(spec, layout="sliced")
     assert g.read_layout("sliced").reshape(3, 9).tolist() == int_matrix("table3_sort3_sy.txt")
-    g = binding.System.from_spec(spec, layout="ell")
-    ell = g.read_layout("ell").reshape(4, 12, 2)
     nid, val = oracle_of(spec, orc.SEM_STANDARD).ell()   # pinned to Table 2
-    assert np.array_equal(ell[..., 0], nid) and np.array_equal(ell[..., 1], val)
+    for rows in (False, True):
+        g = binding.System.from_spec(spec, layout="ell", ell_rows=rows)
+        ell = g.read_layout("ell").reshape(4, 12, 2)
+        assert np.array_equal(ell[..., 0], nid) and np.array_equal(ell[..., 1], val), rows
 
 
 def test_device_layouts_match_oracle_on_random_system(binding):
