@@ -45,7 +45,7 @@ def layout_bytes(layout, q, c, emit_w):
         # in-list offsets, in-lists of receiving neurons, emitted values written + read once
         return 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
     push = 8 * q + 4 * G          # receive buffer read + cleared, one 4-byte update per delivery
-    if layout in ("optimized", "sliced"):
+    if layout in ("optimized", "optimized_columns", "sliced"):
         return push + 4 * (G + E)     # Sy entries of emitters (+ terminator)
     if layout == "ell":
         return push + 8 * (G + E)     # (neuron, value) pairs of emitting rules (+ terminator)
@@ -56,10 +56,18 @@ def step_bytes(layout, q, c, info):
     return state_bytes(q, c, info["rule_bytes"]) + layout_bytes(layout, q, c, info["emit_bits"])
 
 
+def layout_kwargs(layout):
+    """System keyword arguments of a bench layout name ("optimized_columns":
+    the Optimized layout stored neuron by neuron)."""
+    if layout == "optimized_columns":
+        return {"layout": "optimized", "sy_columns": True}
+    return {"layout": layout}
+
+
 def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
     """Times `steps` steps after `warmup` on one system; returns a result dict."""
     t0 = time.time()
-    g = binding.System.from_spec(spec, layout=layout, chunk=chunk)
+    g = binding.System.from_spec(spec, chunk=chunk, **layout_kwargs(layout))
     create_s = time.time() - t0
     info = g.info()
     stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
@@ -89,7 +97,7 @@ def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
 
 
 def count_bytes(binding, spec, layout, steps, warmup, info):
-    g = binding.System.from_spec(spec, layout=layout, counters=True, ring=max(4096, steps + 8))
+    g = binding.System.from_spec(spec, counters=True, ring=max(4096, steps + 8), **layout_kwargs(layout))
     g.step(warmup + steps)
     cnt = g.read_counters(warmup, steps)
     g.close()
@@ -231,7 +239,8 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     return out
 
 
-def run_skewed(binding, torch, steps=500, warmup=16, layouts=("csr_pull", "optimized", "sliced", "csr_push")):
+def run_skewed(binding, torch, steps=500, warmup=16,
+               layouts=("csr_pull", "optimized", "optimized_columns", "sliced", "csr_push")):
     """Config 3: 4,194,304 neurons, power-law out-degree (exponent 2.1, 1..4,096),
     in-degree hubs, hash choice, 500 steps.  ELL is reported analytically (its
     padded matrix, (z+1) x m pairs, exceeds the device memory)."""

@@ -144,7 +144,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
       for (int x = 0; x < 4; ++x) p.add(4LL * nb * nb);
     }
     p.add(4LL * std::max<int64_t>(nnz, 1));
-    if (layout == L_OPT) p.add(4LL * z * q);
+    if (layout == L_OPT) p.add(4LL * ((z + 3) & ~3) * q);
     if (layout == L_SLICED) {  // at most the global height, at most 64 slots per synapse
       const int64_t ns = (q + SLICE - 1) / SLICE;
       p.add(8 * (ns + 1));
@@ -545,6 +545,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   d.sem = o.semantics;
   d.flags = o.flags & (SNP_F_DIGEST | SNP_F_COUNTERS);
   d.ell_rows = (o.flags & SNP_F_ELL_ROWS) ? 1 : 0;
+  d.sy_rows = (o.flags & SNP_F_SY_COLUMNS) ? 0 : 1;
   d.seed = o.seed;
   d.ring = o.ring;
   d.emit_w = emit_width(pmax_all);
@@ -712,8 +713,11 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       d.sy = sy;
       if (hipSuccess != launch_build_sy_sliced(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy_sliced"));
     } else if (o.layout == SNP_LAYOUT_OPTIMIZED) {
-      int32_t* sy = (int32_t*)s->dalloc(4 * (size_t)z * q);
-      if (!sy) return bail(fail(SNP_ENOMEM, "Sy does not fit in device memory"));
+      // neuron by neuron, every column padded to a multiple of 4 entries with nulls
+      const size_t rows = d.sy_rows ? (size_t)z : (size_t)((z + 3) & ~3);
+      int32_t* sy = nullptr;
+      if ((st = alloc_fill(s, (void**)&sy, 4 * std::max<size_t>(rows * (size_t)q, 1), 0xFF)) != SNP_OK)
+        return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "Sy does not fit in device memory") : st);
       d.sy = sy;
       if (hipSuccess != launch_build_sy(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy"));
     } else if (o.layout == SNP_LAYOUT_ELL) {
@@ -1010,7 +1014,11 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
   HIPCHK(hipStreamSynchronize(s->stream));
   if (which == SNP_LAYOUT_OPTIMIZED) {
     if (!s->d.sy || s->d.layout != L_OPT) return fail(SNP_EINVAL, "handle does not use the Optimized layout");
-    HIPCHK(hipMemcpy(out, s->d.sy, 4 * (size_t)need, hipMemcpyDeviceToHost));
+    const size_t dev = (size_t)(s->d.sy_rows ? z : (z + 3) & ~3) * (size_t)q;
+    std::vector<int32_t> tmp(std::max<size_t>(dev, 1));
+    HIPCHK(hipMemcpy(tmp.data(), s->d.sy, 4 * dev, hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < q; ++i)
+      for (int32_t r = 0; r < z; ++r) out[(int64_t)r * q + i] = tmp[(size_t)sy_index(s->d, i, r)];
   } else if (which == SNP_LAYOUT_SLICED) {
     if (!s->d.sy || s->d.layout != L_SLICED) return fail(SNP_EINVAL, "handle does not use the sliced layout");
     const int64_t ns = ((int64_t)q + SLICE - 1) / SLICE;

@@ -81,6 +81,7 @@ struct SysDev {
   const int2* ell;           // ELL: (neuron, value) pairs, (-1, 0) = null; [m][z+1] (a rule's
                              //   column contiguous) or, with ell_rows, [z+1][m]
   int32_t ell_rows;
+  int32_t sy_rows;           // OPTIMIZED: 1 = [z][q], 0 = [q][z4] (columns of z rounded up to 4)
   const int32_t* out_ptr;    // CSR_PUSH: [q+1]
   const int32_t* out_col;    // CSR_PUSH: [nnz]
   const int32_t* out_deg;    // counters only: [q]
@@ -120,6 +121,11 @@ struct SysDev {
 __host__ __device__ inline int64_t ell_index(const SysDev& s, int32_t slot, int32_t row) {
   // rule by rule: each column holds z + 1 pairs rounded up to an even count
   return s.ell_rows ? (int64_t)row * s.m + slot : (int64_t)slot * ((s.z + 2) & ~1) + row;
+}
+
+// Entry (neuron i, row) of the global Sy.
+__host__ __device__ inline int64_t sy_index(const SysDev& s, int32_t i, int32_t row) {
+  return s.sy_rows ? (int64_t)row * s.q + i : (int64_t)i * ((s.z + 3) & ~3) + row;
 }
 
 // Host-side launchers (defined in snp_kernels.hip).

@@ -227,12 +227,12 @@ hipError_t launch_recv_counts(const SysDev& s, int32_t rbuf, unsigned long long*
 // --------------------------------------------------- layout expansion --
 
 // Sy (Table 3): column i = out-neighbours of neuron i in increasing id, -1
-// padding; stored row-major [z][q] so that a row is contiguous over neurons.
+// padding; stored neuron by neuron or row by row, see sy_index.
 __global__ void build_sy_kernel(SysDev s, int32_t* sy) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.q) return;
   const int32_t e0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - e0;
-  for (int32_t r = 0; r < s.z; ++r) sy[(int64_t)r * s.q + i] = r < deg ? s.out_col[e0 + r] : -1;
+  for (int32_t r = 0; r < s.z; ++r) sy[sy_index(s, i, r)] = r < deg ? s.out_col[e0 + r] : -1;
 }
 
 hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st) {

@@ -134,7 +134,7 @@ __device__ __forceinline__ void bin_put(const BinLds& L, uint32_t* bc, int32_t t
 template <int LAYOUT>
 __device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t rule, int32_t v, int64_t e0,
                                           int32_t jj) {
-  if (LAYOUT == L_OPT) return make_int2(s.sy[(int64_t)jj * s.q + i], v);
+  if (LAYOUT == L_OPT) return make_int2(s.sy[sy_index(s, i, jj)], v);
   if (LAYOUT == L_SLICED) return make_int2(s.sy[e0 + (int64_t)jj * SLICE], v);
   if (LAYOUT == L_ELL) return s.ell[ell_index(s, rule, jj + 1)];
   return make_int2(s.out_col[e0 + jj], v);
@@ -147,7 +147,22 @@ __device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t ru
 template <int LAYOUT>
 __device__ __forceinline__ void bin_load(const SysDev& s, int32_t i, int32_t rule, int32_t v, int64_t e0,
                                          int32_t jb, int32_t jend, int2* x) {
-  static_assert(BIN_ROWS == 8, "the ELL path loads 8 entries");
+  static_assert(BIN_ROWS == 8, "the ELL and Sy paths load 8 entries");
+  if (LAYOUT == L_OPT && !s.sy_rows) {
+    // a neuron's Sy column: z rounded up to 4 entries, 16-byte aligned
+    const int32_t zs = (s.z + 3) & ~3;
+    const int4* col = reinterpret_cast<const int4*>(s.sy + (int64_t)i * zs);
+    int4 pr[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int32_t p = (jb >> 2) + u;
+      pr[u] = 4 * p + 3 < zs ? col[p] : make_int4(-1, -1, -1, -1);
+    }
+    const int32_t t8[8] = {pr[0].x, pr[0].y, pr[0].z, pr[0].w, pr[1].x, pr[1].y, pr[1].z, pr[1].w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = make_int2(jb + u < jend ? t8[u] : -1, v);
+    return;
+  }
   if (LAYOUT == L_ELL && !s.ell_rows) {
     const int32_t zs = (s.z + 2) & ~1;
     const int4* col = reinterpret_cast<const int4*>(s.ell + (int64_t)rule * zs);

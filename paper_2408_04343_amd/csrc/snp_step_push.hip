@@ -54,7 +54,7 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
     int32_t deg = 0;
     if (LAYOUT == L_OPT) {
       for (int32_t r = 0; r < s.z; ++r) {
-        const int32_t t = s.sy[(int64_t)r * s.q + i];
+        const int32_t t = s.sy[sy_index(s, i, r)];
         if (t < 0) break;
         atomicAdd(&cur[t], o.emit);
         ++deg;

@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 # emitted values from device memory (plain "csr_pull" stages them in LDS at
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
 # device-wide atomic adds
-LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "sliced", "ell", "ell_rows",
-           "csr_push", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
+LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "optimized_columns", "sliced", "ell",
+           "ell_rows", "csr_push", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
 
 
 def lk(layout):
@@ -28,6 +28,8 @@ def lk(layout):
         return {"layout": layout[:-len("_atomic")], "push_mode": "atomic"}
     if layout == "ell_rows":   # ELL stored row by row (Table 2's drawing) instead of rule by rule
         return {"layout": "ell", "ell_rows": True}
+    if layout == "optimized_columns":   # Sy stored neuron by neuron instead of row by row
+        return {"layout": "optimized", "sy_columns": True}
     return {"layout": layout}
 SEMS = [("standard", orc.SEM_STANDARD), ("paper_kernel", orc.SEM_PAPER_KERNEL)]
 
@@ -151,9 +153,10 @@ def test_many_rules_every_step(binding, layout, select):
 def test_layouts_built_on_device_match_tables(binding):
     from tests._golden import int_matrix
     spec = wl.sort_system([3, 1, 2])
-    g = binding.System.from_spec(spec, layout="optimized")
-    sy = g.read_layout("optimized").reshape(3, 9)
-    assert sy.tolist() == int_matrix("table3_sort3_sy.txt")
+    for cols in (False, True):
+        g = binding.System.from_spec(spec, layout="optimized", sy_columns=cols)
+        sy = g.read_layout("optimized").reshape(3, 9)
+        assert sy.tolist() == int_matrix("table3_sort3_sy.txt"), cols
     g = binding.System.from_spec(spec, layout="sliced")
     assert g.read_layout("sliced").reshape(3, 9).tolist() == int_matrix("table3_sort3_sy.txt")
     nid, val = oracle_of(spec, orc.SEM_STANDARD).ell()   # pinned to Table 2
