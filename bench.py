@@ -337,32 +337,65 @@ def cpu_baseline(spec, seconds):
             "sample": "%s: first %d steps, single-threaded C oracle (%.1f s)" % (spec.name, n, dt)}
 
 
-KERNEL_SOURCES = ["paper_2408_04343_amd/csrc/snp_step_pull.h", "paper_2408_04343_amd/csrc/snp_step_pull.hip",
-                  "paper_2408_04343_amd/csrc/snp_device.h",
-                  "paper_2408_04343_amd/csrc/snp_internal.h"]
+_COMMON = ["paper_2408_04343_amd/csrc/snp_device.h", "paper_2408_04343_amd/csrc/snp_internal.h"]
+KERNEL_SOURCES = {
+    "step_pull_kernel": ["paper_2408_04343_amd/csrc/snp_step_pull.h",
+                         "paper_2408_04343_amd/csrc/snp_step_pull.hip"] + _COMMON,
+    "step_bin_kernel": ["paper_2408_04343_amd/csrc/snp_step_bin.hip"] + _COMMON,
+    "step_push_kernel": ["paper_2408_04343_amd/csrc/snp_step_push.hip"] + _COMMON,
+}
 
 
-def kernel_source_hash():
+def step_kernel(layout, info):
+    """Name of the kernel that runs a step of a system with this info."""
+    if layout == "csr_pull":
+        return "step_pull_kernel"
+    return "step_bin_kernel" if info.get("push_mode") == 2 else "step_push_kernel"
+
+
+def kernel_source_hash(kernel="step_pull_kernel"):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the pull step kernel from the committed
+def traffic_path(kernel, layout):
+    return os.path.join(ROOT, "profiles", "traffic_%s_%s_config2.json" % (kernel, layout))
+
+
+def measured_traffic(kernel="step_pull_kernel", layout="csr_pull"):
+    """HBM bytes per launch of a step kernel on config 2 from the committed
     rocprofv3 counter summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_step_pull_kernel_config2.json")
     try:
-        with open(path) as fh:
+        with open(traffic_path(kernel, layout)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None, None
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash(kernel):
         return None, t
     return t.get("traffic_bytes_per_launch"), t
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy rate (bytes read + written per second)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def _pmc_per_kernel(csv_path, counter):
@@ -376,7 +409,7 @@ def _pmc_per_kernel(csv_path, counter):
     return out
 
 
-def write_traffic(run_dir, copy_dir, kernel, out_path, skip=8):
+def write_traffic(run_dir, copy_dir, kernel, layout, skip=8):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of this
     bench (FETCH_SIZE in run_dir/fetch, WRITE_SIZE in run_dir/write) and of
     the copy probe of 512 MiB (same layout under copy_dir), each counter scaled by what
@@ -395,14 +428,14 @@ def write_traffic(run_dir, copy_dir, kernel, out_path, skip=8):
     write_scale = copy_bytes / (float(np.median(copy_w)) * 1024)
     fk = np.array(kf[0][skip:]) * 1024 * fetch_scale
     wk = np.array(kw[0][skip:]) * 1024 * write_scale
-    t = {"kernel": kernel, "source_hash": kernel_source_hash(),
+    t = {"kernel": kernel, "layout": layout, "workload": "config2", "source_hash": kernel_source_hash(kernel),
          "launches": int(fk.size), "fetch_kib_raw_mean": float(np.mean(kf[0][skip:])),
          "write_kib_raw_mean": float(np.mean(kw[0][skip:])),
          "copy_fetch_kib_raw": float(np.median(copy_f)), "copy_write_kib_raw": float(np.median(copy_w)),
          "fetch_scale": fetch_scale, "write_scale": write_scale,
          "read_bytes_per_launch": float(np.mean(fk)), "write_bytes_per_launch": float(np.mean(wk)),
          "traffic_bytes_per_launch": float(np.mean(fk) + np.mean(wk))}
-    with open(out_path, "w") as fh:
+    with open(traffic_path(kernel, layout), "w") as fh:
         json.dump(t, fh, indent=1)
     print(json.dumps(t))
 
@@ -442,8 +475,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
-    ap.add_argument("--write-traffic", nargs=4, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "OUT"),
-                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the traffic file")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "LAYOUT"),
+                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the traffic file of a layout")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic)
@@ -479,20 +512,32 @@ def main():
             if lay == args.layout:
                 r["mean_counters"] = {k: float(np.mean([c[k] for c in cnt])) for k in cnt[0]}
         r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+        r["kernel"] = step_kernel(lay, r["info"])
+        tb, _t = measured_traffic(r["kernel"], lay)
+        if tb is not None:
+            r["traffic_bytes_per_step"] = tb
+            r["measured_GBps"] = tb / (r["ms_per_step"] * 1e-3) / 1e9
+            r["measured_frac_of_peak"] = r["measured_GBps"] / HBM_PEAK_GBS
         results[lay] = r
         log("%-10s %.4f ms/step  %.3e nu/s  %s" % (lay, r["ms_per_step"], r["neuron_updates_per_s"],
                                                    "%.0f GB/s alg" % r["alg_GBps"] if "alg_GBps" in r else ""))
     head = results[args.layout]
     value = spec.q * args.steps / (head["total_ms"] * 1e-3)
     roof = None
-    traffic, _tinfo = measured_traffic() if args.layout == "csr_pull" else (None, None)
+    traffic = head.get("traffic_bytes_per_step")
+    copy_gbps = copy_bandwidth(torch)
+    log("copy bandwidth %.0f GB/s" % copy_gbps)
+    for r in results.values():
+        if "alg_GBps" in r:
+            r["alg_frac_of_copy"] = r["alg_GBps"] / copy_gbps
+        if "measured_GBps" in r:
+            r["measured_frac_of_copy"] = r["measured_GBps"] / copy_gbps
     if "alg_GBps" in head:
         roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(head["frac_of_peak"], 4),
                 "traffic": None if traffic is None else int(traffic),
-                "kernel": ("step_pull_kernel" if args.layout == "csr_pull" else
-                           "step_bin_kernel" if head["info"].get("push_mode") == binding.PUSH_BINNED
-                           else "step_push_kernel"),
+                "kernel": head["kernel"],
+                "copy_GBps": round(copy_gbps, 1),
                 "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
                 "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}
     batched = None
