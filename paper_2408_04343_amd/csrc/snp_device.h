@@ -78,8 +78,10 @@ constexpr int kPrefetch = RB == 8 ? 4 : 2;
 __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   if (r.period == 0) return n == r.lo;
   if (n < r.lo) return false;
-  if (r.period == 1) return true;
-  return ((uint32_t)(n - r.lo) % (uint32_t)r.period) == 0u;
+  const uint32_t d = (uint32_t)(n - r.lo), per = (uint32_t)r.period;
+  // a power-of-two period (1, 2, 4, ...) needs no division
+  if ((per & (per - 1u)) == 0u) return (d & (per - 1u)) == 0u;
+  return d % per == 0u;
 }
 
 // What a neuron needs to take its step, loaded ahead of its use.  The rule

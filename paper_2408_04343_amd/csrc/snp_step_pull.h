@@ -149,6 +149,18 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
           const uint4 y = pe4[min(vu, v1 - 1)];
           x[u] = vu < v1 ? y : make_uint4(~0u, ~0u, ~0u, ~0u);
         }
+        // all sixteen LDS reads are issued before the first is used
+        uint32_t wv[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            // padding records read word 0, which exists
+            const uint32_t bit = xs[h] == 0xFFFFFFFFu ? 0u : (xs[h] >> PULL_TBITS) * W;
+            wv[u][h] = chunk[bit >> 5];
+          }
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
@@ -156,7 +168,7 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
           for (int h = 0; h < 4; ++h) {
             if (xs[h] == 0xFFFFFFFFu) continue;
             const uint32_t bit = (xs[h] >> PULL_TBITS) * W;
-            const uint32_t val = (chunk[bit >> 5] >> (bit & 31)) & VMASK;
+            const uint32_t val = (wv[u][h] >> (bit & 31)) & VMASK;
             if (val) atomicAdd(&acc[xs[h] & (PULL_TILE - 1)], (int32_t)val);
           }
         }
