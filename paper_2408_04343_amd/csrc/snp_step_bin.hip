@@ -286,27 +286,25 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     if (DIG && k > 0)
       dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
     if (defer_select<RB>(s, in[r])) {
-      L.acc[lt] = C;  // the reception has been read: the slot carries the count to the wave
+      // many rules: listed for a wave; the count travels in the reception slot
+      L.acc[lt] = C;
       L.defer[atomicAdd(ndefer, 1)] = (uint16_t)lt;
-      continue;
     }
-    o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt);
-    anyact |= o[r].act;
   }
   if (s.sel_wave) {
-    // neurons with many rules: a wave per neuron chooses, the owner applies
     __syncthreads();
     wave_select_pass<RB, BIN_NT>(s, t0, k, L.acc, L.defer, *ndefer);
     __syncthreads();
+  }
+  // selection and delays: one place for every neuron, the rule of a listed
+  // neuron already chosen by its wave
 #pragma unroll
-    for (int r = 0; r < BIN_NPT; ++r) {
-      const int32_t lt = tid + r * BIN_NT;
-      const int32_t t = t0 + lt;
-      if (t < s.q && defer_select<RB>(s, in[r])) {
-        o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt, L.acc[lt]);
-        anyact |= o[r].act;
-      }
-    }
+  for (int r = 0; r < BIN_NPT; ++r) {
+    const int32_t lt = tid + r * BIN_NT;
+    const int32_t t = t0 + lt;
+    if (t >= s.q) continue;
+    o[r] = select_update<RB, CNT>(s, t, k, in[r], cnt, defer_select<RB>(s, in[r]) ? L.acc[lt] : CHOOSE_HERE);
+    anyact |= o[r].act;
   }
   const unsigned long long am = __ballot(anyact);
   if (am && (tid & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;

@@ -195,6 +195,8 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
       }
     }
   };
+  // reception folded into the counts; neurons with many rules are listed
+  // for a wave each (their count travels in the reception slot)
 #pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
     const int32_t lt = tid + r * PULL_NT;
@@ -218,28 +220,25 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     in[r].C = C;
     if (DIG && k > 0)
       dig += digest_term(t, C, (int32_t)(in[r].meta & META_D), spiking_id(s, (int32_t)((k - 1) & 1), t));
-    if (defer_select<RB>(s, in[r])) {
-      if (MODE == PM_WIDE) {
-        emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt, s.hsel[t]));
-        continue;
-      }
-      acc[lt] = C;  // the reception has been read: the slot carries the count to the wave
+    if (MODE != PM_WIDE && defer_select<RB>(s, in[r])) {
+      acc[lt] = C;
       defer[atomicAdd(ndefer, 1)] = (uint16_t)lt;
-      continue;
     }
-    emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt));
   }
   if (MODE != PM_WIDE && s.sel_wave) {
-    // neurons with many rules: a wave per neuron chooses, the owner applies
     __syncthreads();
     wave_select_pass<RB, PULL_NT>(s, t0, k, acc, defer, *ndefer);
     __syncthreads();
+  }
+  // selection and delays: one place for every neuron, the rule of a listed
+  // neuron already chosen (by its wave, or before this kernel when wide)
 #pragma unroll
-    for (int r = 0; r < PULL_NPT; ++r) {
-      const int32_t lt = tid + r * PULL_NT;
-      const int32_t t = t0 + lt;
-      if (t < s.q && defer_select<RB>(s, in[r])) emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt, acc[lt]));
-    }
+  for (int r = 0; r < PULL_NPT; ++r) {
+    const int32_t lt = tid + r * PULL_NT;
+    const int32_t t = t0 + lt;
+    if (t >= s.q) continue;
+    const int32_t chosen = !defer_select<RB>(s, in[r]) ? CHOOSE_HERE : MODE == PM_WIDE ? s.hsel[t] : acc[lt];
+    emit_one(r, select_update<RB, CNT>(s, t, k, in[r], cnt, chosen));
   }
   const unsigned long long am = __ballot(anyact);
   if (am && (tid & 63) == (__ffsll((long long)am) - 1)) s.ctl->active[k % 3] = 1;
