@@ -524,6 +524,32 @@ def test_synapse_plasticity_every_step(binding, layout):
     g.close()
 
 
+@pytest.mark.parametrize("memory", ["torch", "hip"])
+def test_layout_beyond_device_memory_is_enomem(binding, memory):
+    # one neuron with 4,095 synapses and 10.5 M rules: ELL needs 4,096 rows
+    # x 10.5 M columns x 8 B = 344 GB, more than the device's 288 GiB
+    q, m = 4096, 10_500_000
+    rules = np.zeros((m, 6), np.int32)
+    rules[:, 0] = np.arange(m) % q
+    rules[:, 1] = 1
+    rules[:, 3] = 1
+    rules[:, 4] = 1
+    src = np.zeros(q - 1, np.int32)
+    dst = np.arange(1, q, dtype=np.int32)
+    s0 = np.ones(q, np.int32)
+    with pytest.raises(binding.SnpError) as ei:
+        binding.System(q, s0, rules, src, dst, layout="ell", memory=memory)
+    assert ei.value.status == -2
+    # the same system in the pull layout fits and runs as the oracle does
+    g = binding.System(q, s0, rules, src, dst, layout="csr_pull", memory=memory)
+    g.step(3)
+    o = orc.OracleSystem(q, s0, rules, src, dst, orc.SEM_STANDARD, wl.SELECT_FIRST, 0)
+    o.step(3)
+    assert g.steps_done() == (o.steps_done, o.halted)
+    assert np.array_equal(g.read_config(), o.read()["C"])
+    g.close()
+
+
 def test_batch_rejects_wide_members(binding):
     a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", pull_mode="wide")
     with pytest.raises(binding.SnpError) as ei:
