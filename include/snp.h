@@ -62,6 +62,11 @@ extern "C" {
  * tall as its own largest out-degree (Sec. 4 pads every column to the global
  * MaxOutDegree, which a few hub neurons make enormous).                     */
 #define SNP_LAYOUT_SLICED    5
+/* The paper's baseline representation (Sec. 3, Alg. 3): the transition
+ * matrix stored whole, m x q 32-bit entries (the spikes a rule sends to each
+ * neuron; the consumption is applied by the owning neuron).  A step reads
+ * the full row of every emitting rule.  For small systems and comparisons. */
+#define SNP_LAYOUT_SPARSE    6
 
 /* Choice among the applicable rules of an open neuron (Sec. 5.2 replaces
  * SAMPLE_ONE by the first applicable rule):
@@ -269,6 +274,9 @@ int snp_set_synapses(snp_sys* sys, int64_t nsyn, const int32_t* syn_src, const i
 /* Device copy of the representation, for inspection (host buffers):
  *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
  *   which = SNP_LAYOUT_SLICED: the slices expanded to the same [z][q] Sy;
+ *   which = SNP_LAYOUT_SPARSE: the transition matrix M as [m][q] int32, rows
+ *           in caller rule id order (Table 1: -c at the owner, +p at each
+ *           target);
  *   which = SNP_LAYOUT_ELL: M^s as [z'][m][2] int32 (neuron, value), columns
  *           in caller rule id order;
  *   which = SNP_LAYOUT_CSR_PUSH: out-neighbour row starts [q+1] then targets.

@@ -16,13 +16,15 @@ import numpy as np
 
 from . import build as _build
 
-LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL, LAYOUT_SLICED = 0, 1, 2, 3, 4, 5
+LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL, LAYOUT_SLICED, LAYOUT_SPARSE = \
+    0, 1, 2, 3, 4, 5, 6
 SELECT_FIRST, SELECT_HASH = 0, 1
 SEM_STANDARD, SEM_PAPER_KERNEL = 0, 1
 F_DIGEST, F_COUNTERS, F_NO_GRAPH, F_WIDE_RULES, F_ELL_ROWS, F_SY_COLUMNS = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 
 LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL,
-           "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL, "sliced": LAYOUT_SLICED}
+           "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL, "sliced": LAYOUT_SLICED,
+           "sparse": LAYOUT_SPARSE}
 SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
 SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
 PULL_AUTO, PULL_STAGED, PULL_GATHER, PULL_WIDE = 0, 1, 2, 3

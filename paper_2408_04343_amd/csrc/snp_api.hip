@@ -145,6 +145,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
     }
     p.add(4LL * std::max<int64_t>(nnz, 1));
     if (layout == L_OPT) p.add(4LL * ((z + 3) & ~3) * q);
+    if (layout == L_SPARSE) p.add(4LL * std::max(m, 1) * q);
     if (layout == L_SLICED) {  // at most the global height, at most 64 slots per synapse
       const int64_t ns = (q + SLICE - 1) / SLICE;
       p.add(8 * (ns + 1));
@@ -369,7 +370,7 @@ int snp_footprint(int32_t q, int32_t m, int64_t nsyn, int32_t zmax, int32_t layo
                   int64_t ring, int64_t* bytes) {
   if (q < 1 || m < 0 || nsyn < 0 || zmax < 0 || !bytes) return fail(SNP_EINVAL, "bad shape");
   if (layout == SNP_LAYOUT_AUTO) layout = SNP_LAYOUT_CSR_PULL;
-  if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_SLICED) return fail(SNP_EINVAL, "bad layout");
+  if (layout < SNP_LAYOUT_OPTIMIZED || layout > SNP_LAYOUT_SPARSE) return fail(SNP_EINVAL, "bad layout");
   *bytes = plan_bytes(q, m, nsyn, zmax, layout, flags, ring > 0 ? ring : kDefaultRing, 16, -1);
   return SNP_OK;
 }
@@ -387,7 +388,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   if (!spikes0 || (m > 0 && !rules) || (nsyn > 0 && (!syn_src || !syn_dst)))
     return fail(SNP_EINVAL, "null array");
   if (o.layout == SNP_LAYOUT_AUTO) o.layout = SNP_LAYOUT_CSR_PULL;
-  if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_SLICED) return fail(SNP_EINVAL, "bad layout");
+  if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_SPARSE) return fail(SNP_EINVAL, "bad layout");
   if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
   if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_WIDE) return fail(SNP_EINVAL, "bad pull_mode");
   if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_BINNED) return fail(SNP_EINVAL, "bad push_mode");
@@ -695,7 +696,13 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.out_ptr = p;
     if ((st = upload(s, &p, oc.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
     d.out_col = p;
-    if (o.layout == SNP_LAYOUT_SLICED) {
+    if (o.layout == SNP_LAYOUT_SPARSE) {
+      int32_t* dense = nullptr;
+      if ((st = alloc_fill(s, (void**)&dense, 4 * (size_t)std::max(m, 1) * (size_t)q, 0)) != SNP_OK)
+        return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "the dense matrix does not fit in device memory") : st);
+      d.dense = dense;
+      if (hipSuccess != launch_build_dense(d, dense, s->stream)) return bail(fail(SNP_EDEVICE, "build_dense"));
+    } else if (o.layout == SNP_LAYOUT_SLICED) {
       const int64_t ns = ((int64_t)q + SLICE - 1) / SLICE;
       std::vector<int64_t> off((size_t)ns + 1, 0);
       for (int64_t b = 0; b < ns; ++b) {
@@ -1004,6 +1011,7 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
   const int32_t q = s->q, m = s->m, z = s->z;
   int64_t need = 0;
   if (which == SNP_LAYOUT_OPTIMIZED || which == SNP_LAYOUT_SLICED) need = (int64_t)z * q;
+  else if (which == SNP_LAYOUT_SPARSE) need = (int64_t)m * q;
   else if (which == SNP_LAYOUT_ELL) need = 2LL * (z + 1) * m;
   else if (which == SNP_LAYOUT_CSR_PUSH) need = (int64_t)q + 1 + s->nnz;
   else if (which == SNP_LAYOUT_CSR_PULL) need = (int64_t)q + 1 + s->nnz;
@@ -1019,6 +1027,17 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
     HIPCHK(hipMemcpy(tmp.data(), s->d.sy, 4 * dev, hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < q; ++i)
       for (int32_t r = 0; r < z; ++r) out[(int64_t)r * q + i] = tmp[(size_t)sy_index(s->d, i, r)];
+  } else if (which == SNP_LAYOUT_SPARSE) {
+    if (!s->d.dense) return fail(SNP_EINVAL, "handle does not use the Sparse layout");
+    const snp_sys* root = s->base ? s->base : s;
+    std::vector<int32_t> tmp((size_t)std::max<int64_t>(need, 1));
+    HIPCHK(hipMemcpy(tmp.data(), s->d.dense, 4 * (size_t)need, hipMemcpyDeviceToHost));
+    for (int32_t sl = 0; sl < m; ++sl) {
+      const int32_t id = root->h_rid[sl];
+      std::memcpy(out + (int64_t)id * q, tmp.data() + (int64_t)sl * q, 4 * (size_t)q);
+      const snp_rule& R = root->h_rules[id];
+      out[(int64_t)id * q + R.neuron] = -R.c;   // consumption at the owner (Table 1)
+    }
   } else if (which == SNP_LAYOUT_SLICED) {
     if (!s->d.sy || s->d.layout != L_SLICED) return fail(SNP_EINVAL, "handle does not use the sliced layout");
     const int64_t ns = ((int64_t)q + SLICE - 1) / SLICE;

@@ -6,7 +6,7 @@
 
 namespace snp {
 
-enum : int32_t { L_OPT = 1, L_ELL = 2, L_CSR_PUSH = 3, L_CSR_PULL = 4, L_SLICED = 5 };
+enum : int32_t { L_OPT = 1, L_ELL = 2, L_CSR_PUSH = 3, L_CSR_PULL = 4, L_SLICED = 5, L_SPARSE = 6 };
 constexpr int32_t SLICE = 64;           // neurons per slice of the sliced Optimized layout
 enum : int32_t { SEL_FIRST = 0, SEL_HASH = 1 };
 enum : int32_t { SEM_STANDARD = 0, SEM_PAPER = 1 };
@@ -76,6 +76,7 @@ struct SysDev {
   // push representations
   int32_t* delta[2];         // spikes received at step k, by k & 1
   const int32_t* sy;         // OPTIMIZED: [z][q] row-major, -1 = null; SLICED: the slices
+  const int32_t* dense;      // SPARSE: [m][q] spikes rule slot r sends to neuron t
   const int64_t* sy_off;     // SLICED: [q/64 + 1] first entry of each slice; slice b is
                              //   [h_b][64] row-major, h_b = (sy_off[b+1] - sy_off[b]) / 64
   const int2* ell;           // ELL: (neuron, value) pairs, (-1, 0) = null; [m][z+1] (a rule's
@@ -168,6 +169,7 @@ hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, i
                          unsigned long long* out, hipStream_t st);
 hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st);
 hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st);
+hipError_t launch_build_dense(const SysDev& s, int32_t* dense, hipStream_t st);
 hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st);
 hipError_t launch_restore(const SysDev& s, int32_t sbuf, const int32_t* C, const int32_t* D,
                           const int32_t* P, const int32_t* S, const int32_t* slot_of_rule,

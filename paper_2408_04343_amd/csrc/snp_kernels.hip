@@ -250,6 +250,27 @@ __global__ void build_sy_sliced_kernel(SysDev s, int32_t* sy) {
   for (int64_t r = 0; r < h; ++r) sy[b0 + r * SLICE + i % SLICE] = r < deg ? s.out_col[e0 + r] : -1;
 }
 
+// Dense transition matrix (Alg. 3's representation) without the -c entries:
+// row of rule slot r = p_r at each out-neighbour of its neuron (zeros
+// elsewhere, cleared beforehand).
+template <int RB>
+__global__ void build_dense_kernel(SysDev s, int32_t* dense) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.q) return;
+  const int32_t e0 = s.out_ptr[i], e1 = s.out_ptr[i + 1];
+  for (int32_t r = s.rs[i]; r < s.rs[i + 1]; ++r) {
+    const int32_t p = load_rule<RB>(s, r).p;
+    if (p > 0)
+      for (int32_t e = e0; e < e1; ++e) dense[(int64_t)r * s.q + s.out_col[e]] = p;
+  }
+}
+
+hipError_t launch_build_dense(const SysDev& s, int32_t* dense, hipStream_t st) {
+  if (s.rule_bytes == 8) build_dense_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
+  else build_dense_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st) {
   build_sy_sliced_kernel<<<(s.q + 255) / 256, 256, 0, st>>>(s, sy);
   return hipGetLastError();

@@ -1,4 +1,4 @@
-// Binned push form of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH layouts) for gfx950.
+// Binned push form of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH, SPARSE layouts) for gfx950.
 //
 // The STEP of Algorithms 4 and 5 adds, for every emitting rule or neuron, its
 // spikes into the configuration of each target with atomics (Sec. 5).  Here a
@@ -201,6 +201,17 @@ __device__ __forceinline__ void bin_walk(const SysDev& s, const BinLds& L, uint3
   }
 }
 
+// Entries j0, j0 + stride, ... of row `rule` of the dense matrix (Alg. 3):
+// every nonzero entry is a synapse.
+__device__ __forceinline__ void bin_walk_dense(const SysDev& s, const BinLds& L, uint32_t* bc, int32_t rule,
+                                               int32_t j0, int32_t stride) {
+  const int32_t* row = s.dense + (int64_t)rule * s.q;
+  for (int32_t jj = j0; jj < s.q; jj += stride) {
+    const int32_t v = row[jj];
+    if (v) bin_put(L, bc, jj, v);
+  }
+}
+
 // Start and row bound of the walk of neuron i: CSR, its row start and
 // out-degree; sliced Sy, its column's first entry and the slice height;
 // Sy and ELL, the layout height (their rows end at a null entry, or there).
@@ -315,6 +326,16 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   // rest of each row up to BIN_LIGHT entries in batches of BIN_ROWS.  Longer
   // rows are finished below by the whole block.
   uint32_t* bc = pick(s.bins[0], s.bins[1], k);
+  if (LAYOUT == L_SPARSE) {
+    // every row of the dense matrix is q long: all go to the whole block
+#pragma unroll
+    for (int r = 0; r < BIN_NPT; ++r) {
+      if (o[r].emit <= 0) continue;
+      const int32_t h = atomicAdd(hcount, 1);
+      if (h < BIN_HMAX) L.heavy[h] = make_int2(t0 + tid + r * BIN_NT, o[r].erule);
+      else bin_walk_dense(s, L, bc, o[r].erule, 0, 1);
+    }
+  } else {
   int64_t e0[BIN_NPT];
   int32_t jend[BIN_NPT], rule[BIN_NPT];
 #pragma unroll
@@ -376,6 +397,7 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
       }
     }
   }
+  }
   if (CNT) {
 #pragma unroll
     for (int r = 0; r < BIN_NPT; ++r) {
@@ -390,6 +412,10 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   const int32_t nh = min(*hcount, BIN_HMAX);
   for (int32_t h = 0; h < nh; ++h) {
     const int2 hv = L.heavy[h];
+    if (LAYOUT == L_SPARSE) {
+      bin_walk_dense(s, L, bc, hv.y, tid, BIN_NT);
+      continue;
+    }
     const int32_t i = hv.x;
     const int32_t deg = s.out_ptr[i + 1] - s.out_ptr[i];
     int64_t ce0;
@@ -469,6 +495,7 @@ static hipError_t launch_bin_rf(const SysDev& s, int32_t j, hipStream_t st) {
   switch (s.layout) {
     case L_OPT: step_bin_kernel<L_OPT, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     case L_SLICED: step_bin_kernel<L_SLICED, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
+    case L_SPARSE: step_bin_kernel<L_SPARSE, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     case L_ELL: step_bin_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     case L_CSR_PUSH: step_bin_kernel<L_CSR_PUSH, RB, FL><<<grid, BIN_NT, lds, st>>>(s, j); break;
     default: return hipErrorInvalidValue;
@@ -486,6 +513,9 @@ static hipError_t launch_bin_batch_rf(const SysDev& s, const SysDev* members, co
       break;
     case L_SLICED:
       step_bin_batch_kernel<L_SLICED, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
+      break;
+    case L_SPARSE:
+      step_bin_batch_kernel<L_SPARSE, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);
       break;
     case L_ELL:
       step_bin_batch_kernel<L_ELL, RB, FL><<<grid, BIN_NT, lds, st>>>(members, tiles, ntiles, j);

@@ -1,4 +1,4 @@
-// Push forms of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH layouts) for gfx950:
+// Push forms of the step (OPTIMIZED, SLICED, ELL, CSR_PUSH, SPARSE layouts) for gfx950:
 // emitting neurons add their spikes into the receive buffer of the step.
 #include "snp_device.h"
 
@@ -67,6 +67,16 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
         atomicAdd(&cur[t], o.emit);
         ++deg;
       }
+    } else if (LAYOUT == L_SPARSE) {
+      // the emitting rule's whole row of the dense matrix (Alg. 3)
+      const int32_t* row = s.dense + (int64_t)o.erule * s.q;
+      for (int32_t t = 0; t < s.q; ++t) {
+        const int32_t v = row[t];
+        if (v) {
+          atomicAdd(&cur[t], v);
+          ++deg;
+        }
+      }
     } else if (LAYOUT == L_ELL) {
       for (int32_t r = 1; r <= s.z; ++r) {
         const int2 pr = s.ell[ell_index(s, o.erule, r)];
@@ -122,6 +132,7 @@ static hipError_t launch_push_rf(const SysDev& s, int32_t j, hipStream_t st) {
   switch (s.layout) {
     case L_OPT: step_push_kernel<L_OPT, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     case L_SLICED: step_push_kernel<L_SLICED, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
+    case L_SPARSE: step_push_kernel<L_SPARSE, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     case L_ELL: step_push_kernel<L_ELL, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     case L_CSR_PUSH: step_push_kernel<L_CSR_PUSH, RB, FL><<<grid, PUSH_NT, 0, st>>>(s, j); break;
     default: return hipErrorInvalidValue;
@@ -136,6 +147,9 @@ static hipError_t launch_push_batch_rf(const SysDev& s, const SysDev* members, c
     case L_OPT: step_push_batch_kernel<L_OPT, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j); break;
     case L_SLICED:
       step_push_batch_kernel<L_SLICED, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j);
+      break;
+    case L_SPARSE:
+      step_push_batch_kernel<L_SPARSE, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j);
       break;
     case L_ELL: step_push_batch_kernel<L_ELL, RB, FL><<<grid, PUSH_NT, 0, st>>>(members, tiles, ntiles, j); break;
     case L_CSR_PUSH:

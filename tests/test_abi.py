@@ -45,6 +45,8 @@ def test_footprint_orders():
     assert 0 < pull < opt < ell
     # ELL stores z'+1 (neuron, value) pairs per rule
     assert ell - binding.footprint(q, m, nnz, z, "csr_push") >= 8 * (z + 1) * m
+    # the dense matrix: m x q entries, 11 TB at this size
+    assert binding.footprint(q, m, nnz, z, "sparse") - binding.footprint(q, m, nnz, z, "csr_push") >= 4 * m * q
 
 
 @pytest.mark.parametrize("bad", [

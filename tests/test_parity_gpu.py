@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
 # device-wide atomic adds
 LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "optimized_columns", "sliced", "ell",
-           "ell_rows", "csr_push", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic"]
+           "ell_rows", "csr_push", "sparse", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic",
+           "sparse_atomic"]
 
 
 def lk(layout):
@@ -164,6 +165,26 @@ def test_layouts_built_on_device_match_tables(binding):
         g = binding.System.from_spec(spec, layout="ell", ell_rows=rows)
         ell = g.read_layout("ell").reshape(4, 12, 2)
         assert np.array_equal(ell[..., 0], nid) and np.array_equal(ell[..., 1], val), rows
+
+
+def test_dense_matrix_matches_table1(binding):
+    from tests._golden import int_matrix
+    spec = wl.sort_system([3, 1, 2])
+    g = binding.System.from_spec(spec, layout="sparse")
+    M = g.read_layout("sparse").reshape(spec.rules.shape[0], spec.q)
+    assert M.tolist() == int_matrix("table1_sort3_M.txt")
+    assert g.info()["layout"] == binding.LAYOUT_SPARSE
+
+
+def test_dense_matrix_matches_oracle_on_random_system(binding):
+    from oracle import dense
+    spec = wl.small_random(6, 700, max_deg=12, max_rules=5)
+    g = binding.System.from_spec(spec, layout="sparse")
+    M = g.read_layout("sparse").reshape(spec.rules.shape[0], spec.q)
+    ref = dense.transition_matrix(spec.q, spec.rules, list(zip(spec.src.tolist(), spec.dst.tolist())))
+    assert np.array_equal(M, ref)
+    # the m x q matrix is what the layout costs on the device
+    assert g.info()["device_bytes"] >= 4 * spec.rules.shape[0] * spec.q
 
 
 def test_device_layouts_match_oracle_on_random_system(binding):
