@@ -324,6 +324,62 @@ def run_sort(binding, torch, sizes=(100, 1000, 5000), layouts=("csr_pull", "slic
     return out
 
 
+RATIO_LAYOUTS = ("sparse", "ell", "optimized", "sparse_binned", "ell_binned", "optimized_binned",
+                 "sparse_atomic", "ell_atomic", "optimized_atomic", "csr_pull")
+# Sec. 6, sorting family at n = 500: time ratios Compressed/Sparse 83x, ELL/Sparse
+# 34x, Compressed/ELL 2.4x; memory: Compressed 10x below Sparse and 7x below ELL
+PAPER_RATIOS_N500 = {"time_sparse_over_optimized": 83.0, "time_sparse_over_ell": 34.0,
+                     "time_ell_over_optimized": 2.4, "mem_sparse_over_optimized": 10.0,
+                     "mem_ell_over_optimized": 7.0}
+
+
+def run_ratios(binding, torch, n=500, layouts=RATIO_LAYOUTS):
+    """The paper's layout comparison (Sec. 6) restated: the sorting family at
+    n inputs in descending order (n .. 1), run to halting under the dense
+    Sparse matrix, ELL and Optimized (each with the schedule AUTO picks, wide
+    at n = 500, then binned and atomic push) and the pull layout; time and
+    device bytes per layout, and the ratios the paper quotes."""
+    from paper_2408_04343_amd import workloads as wl
+    v = np.arange(n, 0, -1)
+    spec = wl.sort_system(v)
+    rows = {}
+    for lay in layouts:
+        base, _, mode = lay.partition("_")
+        kw = {"layout": lay} if lay == "csr_pull" or not mode else {"layout": base, "push_mode": mode}
+        g = binding.System.from_spec(spec, **kw)
+        stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g.step(n + 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        steps, halted = g.steps_done()
+        C = g.read_config()
+        ok = bool(halted and steps == n + 1 and np.array_equal(C[2 * n:], np.sort(v)) and not C[:2 * n].any())
+        info = g.info()
+        rows[lay] = {"ms_total": round(ms, 3), "us_per_step": round(1e3 * ms / max(steps, 1), 3),
+                     "device_bytes": info["device_bytes"], "closed_form_ok": ok,
+                     "pull_mode": info["pull_mode"], "push_mode": info["push_mode"]}
+        g.close()
+        log("ratios n=%d %-16s %.3f ms  %.1f MB  closed form %s" %
+            (n, lay, ms, rows[lay]["device_bytes"] / 1e6, "ok" if ok else "WRONG"))
+
+    def ratio(a, b, key):
+        return round(rows[a][key] / rows[b][key], 2) if a in rows and b in rows else None
+    out = {"n": n, "q": spec.q, "rules": spec.m, "synapses": spec.nnz, "input": "n .. 1", "layouts": rows,
+           "paper_rtx2080": PAPER_RATIOS_N500 if n == 500 else None}
+    for push in ("", "_binned", "_atomic"):
+        sp, el, op = "sparse" + push, "ell" + push, "optimized" + push
+        out["ratios" + push] = {"time_sparse_over_optimized": ratio(sp, op, "ms_total"),
+                                "time_sparse_over_ell": ratio(sp, el, "ms_total"),
+                                "time_ell_over_optimized": ratio(el, op, "ms_total"),
+                                "mem_sparse_over_optimized": ratio(sp, op, "device_bytes"),
+                                "mem_ell_over_optimized": ratio(el, op, "device_bytes")}
+    return out
+
+
 def cpu_baseline(spec, seconds):
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
@@ -472,6 +528,8 @@ def main():
     ap.add_argument("--no-skewed", action="store_true", help="skip the skewed-degree workload")
     ap.add_argument("--sort-n", default="100,1000,5000",
                     help="sizes of the sorting family run to halting ('' to skip)")
+    ap.add_argument("--ratio-n", type=int, default=500,
+                    help="sorting instance of the Sparse/ELL/Optimized comparison (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0)
@@ -546,6 +604,7 @@ def main():
     skewed = None if args.no_skewed else run_skewed(binding, torch)
     sort_sizes = [int(x) for x in args.sort_n.split(",") if x]
     sorting = run_sort(binding, torch, sort_sizes) if sort_sizes else None
+    ratios = None if args.ratio_n <= 0 else run_ratios(binding, torch, args.ratio_n)
     served = None
     if not args.no_serve:
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
@@ -570,6 +629,7 @@ def main():
         "served": served,
         "skewed": skewed,
         "sorting_family": sorting,
+        "layout_ratios": ratios,
         "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
                                 "over": "graph chunks of %d steps" % args.chunk},
         "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()

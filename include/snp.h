@@ -114,10 +114,17 @@ extern "C" {
  * Algorithms 4 and 5 does.  BINNED: the walk over the same layout appends a
  * record per synapse to a region (source tile -> target tile) and the owner
  * of the target tile sums them at the next step; no device-wide atomics.
- * AUTO: BINNED up to 2048 tiles of 4096 neurons, ATOMIC above.             */
+ * WIDE: the atomics of ATOMIC, for few neurons with many rules and long rows
+ * (the sorting family of Sec. 6): one wave per neuron with more than 32
+ * rules chooses among them, one wave per emitting row longer than 32
+ * entries walks it; three launches per step.  Systems in this mode are not
+ * accepted by snp_batch_* (SNP_ENOTSUP).
+ * AUTO: WIDE above 256 K synapses per 4096 neurons, else BINNED up to 2048
+ * tiles of 4096 neurons, else ATOMIC.                                      */
 #define SNP_PUSH_AUTO   0
 #define SNP_PUSH_ATOMIC 1
 #define SNP_PUSH_BINNED 2
+#define SNP_PUSH_WIDE   3
 
 #define SNP_F_DIGEST   0x1u /* keep a digest of every reached state          */
 #define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
@@ -296,7 +303,7 @@ typedef struct snp_info_t {
   int32_t pull_chunk;    /* CSR_PULL: sources per LDS chunk                  */
   int32_t pull_chunks;   /* CSR_PULL: number of source chunks                */
   int32_t pull_mode;     /* CSR_PULL: SNP_PULL_STAGED, _GATHER or _WIDE      */
-  int32_t push_mode;     /* push layouts: SNP_PUSH_ATOMIC or SNP_PUSH_BINNED */
+  int32_t push_mode;     /* push layouts: SNP_PUSH_ATOMIC, _BINNED or _WIDE  */
   int32_t reserved;
   int64_t device_bytes;  /* device memory held by the handle                 */
 } snp_info_t;

@@ -29,8 +29,8 @@ SELECTS = {"first": SELECT_FIRST, "hash": SELECT_HASH}
 SEMANTICS = {"standard": SEM_STANDARD, "paper_kernel": SEM_PAPER_KERNEL}
 PULL_AUTO, PULL_STAGED, PULL_GATHER, PULL_WIDE = 0, 1, 2, 3
 PULL_MODES = {"auto": PULL_AUTO, "staged": PULL_STAGED, "gather": PULL_GATHER, "wide": PULL_WIDE}
-PUSH_AUTO, PUSH_ATOMIC, PUSH_BINNED = 0, 1, 2
-PUSH_MODES = {"auto": PUSH_AUTO, "atomic": PUSH_ATOMIC, "binned": PUSH_BINNED}
+PUSH_AUTO, PUSH_ATOMIC, PUSH_BINNED, PUSH_WIDE = 0, 1, 2, 3
+PUSH_MODES = {"auto": PUSH_AUTO, "atomic": PUSH_ATOMIC, "binned": PUSH_BINNED, "wide": PUSH_WIDE}
 
 # exported symbols, in header order
 SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_read_config",

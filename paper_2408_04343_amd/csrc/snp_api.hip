@@ -90,6 +90,13 @@ bool pull_gathers(int32_t mode, int32_t q, int64_t nsyn, int32_t w) {
   return 2 * (nsyn / tiles) < words || (tiles < 256 && gtiles > tiles && q >= 8192);
 }
 
+// AUTO push: wide above 256 K synapses per 4096-neuron tile (as pull_wide).
+bool push_wide(int32_t mode, int32_t q, int64_t nsyn) {
+  if (mode != SNP_PUSH_AUTO) return mode == SNP_PUSH_WIDE;
+  const int64_t tiles = ((int64_t)q + (1LL << BIN_TB) - 1) >> BIN_TB;
+  return nsyn / tiles > 262144;
+}
+
 struct Plan {
   int64_t bytes = 0;
   void add(int64_t b) { bytes += (b + 255) / 256 * 256; }
@@ -136,6 +143,7 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
   } else {
     if (flags & SNP_F_COUNTERS) p.add(4LL * q);
     p.add(4LL * q * 2);      // delta[2]
+    p.add(24LL * q + 16);    // wide schedule: choices, many-rule list, emitter list and counts
     p.add(4LL * (q + 1));    // out_ptr
     const int64_t nb = (q + (1LL << BIN_TB) - 1) >> BIN_TB;
     if (nb <= BIN_MAX_TILES) {  // binned push: bins, counts, region offsets
@@ -313,6 +321,13 @@ int alloc_state(snp_sys* s, const int32_t* spikes0) {
   } else {
     for (int b = 0; b < 2; ++b)
       if ((st = alloc_fill(s, (void**)&d.delta[b], 4 * (size_t)q, 0)) != SNP_OK) return st;
+    d.elist = nullptr;
+    d.ecnt = nullptr;
+    if (d.push_wide) {
+      if ((st = alloc_fill(s, (void**)&d.hsel, 4 * (size_t)q, 0xFF)) != SNP_OK) return st;
+      if ((st = alloc_fill(s, (void**)&d.elist, 16 * (size_t)q, 0)) != SNP_OK) return st;
+      if ((st = alloc_fill(s, (void**)&d.ecnt, 16, 0)) != SNP_OK) return st;
+    }
     d.bins[0] = d.bins[1] = nullptr;
     d.bcnt[0] = d.bcnt[1] = nullptr;
     if (d.push_binned) {
@@ -391,7 +406,7 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
   if (o.layout < SNP_LAYOUT_OPTIMIZED || o.layout > SNP_LAYOUT_SPARSE) return fail(SNP_EINVAL, "bad layout");
   if (o.select != SNP_SELECT_FIRST && o.select != SNP_SELECT_HASH) return fail(SNP_EINVAL, "bad select");
   if (o.pull_mode < SNP_PULL_AUTO || o.pull_mode > SNP_PULL_WIDE) return fail(SNP_EINVAL, "bad pull_mode");
-  if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_BINNED) return fail(SNP_EINVAL, "bad push_mode");
+  if (o.push_mode < SNP_PUSH_AUTO || o.push_mode > SNP_PUSH_WIDE) return fail(SNP_EINVAL, "bad push_mode");
   if (o.semantics != SNP_SEM_STANDARD && o.semantics != SNP_SEM_PAPER_KERNEL)
     return fail(SNP_EINVAL, "bad semantics");
   if (o.chunk <= 0) o.chunk = kDefaultChunk;
@@ -670,8 +685,19 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     const int64_t nb = ((int64_t)q + (1LL << BIN_TB) - 1) >> BIN_TB;
     if (o.push_mode == SNP_PUSH_BINNED && nb > BIN_MAX_TILES)
       return bail(fail(SNP_ENOTSUP, "binned push: more than 2048 tiles of 4096 neurons"));
-    d.push_binned = (o.push_mode == SNP_PUSH_BINNED || (o.push_mode == SNP_PUSH_AUTO && nb <= BIN_MAX_TILES)) ? 1 : 0;
+    d.push_wide = push_wide(o.push_mode, q, nsyn) ? 1 : 0;
+    d.push_binned = !d.push_wide && (o.push_mode == SNP_PUSH_BINNED ||
+                                     (o.push_mode == SNP_PUSH_AUTO && nb <= BIN_MAX_TILES)) ? 1 : 0;
     d.bnb = d.push_binned ? (int32_t)nb : 0;
+    if (d.push_wide) {
+      // neurons whose rules a wave scans
+      std::vector<int32_t> hv;
+      for (int32_t i = 0; i < q; ++i)
+        if (rs[(size_t)i + 1] - rs[i] > SEL_LIGHT_RULES) hv.push_back(i);
+      if ((st = upload(s, &p, hv.data(), hv.size())) != SNP_OK) return bail(st);
+      d.heavy = p;
+      d.n_heavy = (int32_t)hv.size();
+    }
     if (d.push_binned) {
       // region (b -> t) holds one slot per synapse from tile b into tile t;
       // regions are laid out target-major, so a tile's inbox is contiguous
@@ -960,6 +986,7 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
     if (s->d.push_binned)
       for (int b = 0; b < 2; ++b)
         HIPCHK(hipMemsetAsync(s->d.bcnt[b], 0, 4 * (size_t)s->d.bnb * (size_t)s->d.bnb, s->stream));
+    if (s->d.push_wide) HIPCHK(hipMemsetAsync(s->d.ecnt, 0, 16, s->stream));
   }
   Ctl c;
   std::memset(&c, 0, sizeof(c));
@@ -1090,7 +1117,8 @@ int snp_info(snp_sys* s, snp_info_t* o) {
   o->pull_mode = s->layout != SNP_LAYOUT_CSR_PULL ? 0
                  : s->d.pull_wide ? SNP_PULL_WIDE
                  : s->d.pull_gather ? SNP_PULL_GATHER : SNP_PULL_STAGED;
-  o->push_mode = s->layout == SNP_LAYOUT_CSR_PULL ? 0 : s->d.push_binned ? SNP_PUSH_BINNED : SNP_PUSH_ATOMIC;
+  o->push_mode = s->layout == SNP_LAYOUT_CSR_PULL ? 0 : s->d.push_binned ? SNP_PUSH_BINNED
+                     : s->d.push_wide ? SNP_PUSH_WIDE : SNP_PUSH_ATOMIC;
   o->reserved = 0;
   o->device_bytes = s->device_bytes;
   return SNP_OK;

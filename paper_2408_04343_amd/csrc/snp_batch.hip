@@ -100,8 +100,10 @@ int upload_tables(snp_batch* b) {
   size_t lds[2] = {0, 0};
   for (snp_sys* s : b->members) {
     if (s->d.layout == L_CSR_PULL && s->d.pull_wide)
-    return fail(SNP_ENOTSUP, "systems in the wide pull schedule run alone");
-  const int g = group_of(s->d);
+      return fail(SNP_ENOTSUP, "systems in the wide pull schedule run alone");
+    if (s->d.layout != L_CSR_PULL && s->d.push_wide)
+      return fail(SNP_ENOTSUP, "systems in the wide push schedule run alone");
+    const int g = group_of(s->d);
     tiles[g] += (s->q + step_tile(s->d) - 1) / step_tile(s->d);
     if (s->d.layout == L_CSR_PULL) lds[g] = std::max(lds[g], pull_lds_bytes(s->d));
     else if (s->d.push_binned) lds[g] = std::max(lds[g], bin_lds_bytes(s->d));
@@ -189,6 +191,8 @@ int add_member(snp_batch* b, snp_sys* s) {
   if (s->dev != b->dev) return fail(SNP_EINVAL, "handle on another device");
   if (s->d.layout == L_CSR_PULL && s->d.pull_wide)
     return fail(SNP_ENOTSUP, "systems in the wide pull schedule run alone");
+  if (s->d.layout != L_CSR_PULL && s->d.push_wide)
+    return fail(SNP_ENOTSUP, "systems in the wide push schedule run alone");
   const int g = group_of(s->d);
   const SysDev& any = b->has_proto[0] ? b->proto[0] : b->proto[1];
   if ((b->has_proto[0] || b->has_proto[1]) && !compatible(any, s->d))

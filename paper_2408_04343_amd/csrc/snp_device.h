@@ -208,6 +208,17 @@ __device__ __forceinline__ bool step_prologue(const SysDev& s, int32_t tile, int
   return true;
 }
 
+// Would step k = k_base + j run?  The same test as step_prologue, read-only:
+// for the launches around a step kernel (they see the same answer before
+// and after it, since the step kernel only sets `halted` when it skips).
+__device__ __forceinline__ bool wide_runs(const SysDev& s, int32_t j, int64_t& k) {
+  const Ctl* ctl = s.ctl;
+  k = ctl->k_base + j;
+  if (ctl->halted || k >= ctl->k_limit) return false;
+  if (k > 0 && ctl->active[(k - 1) % 3] == 0) return false;
+  return true;
+}
+
 template <int RB>
 __device__ __forceinline__ void prefetch_neuron(const SysDev& s, int32_t i, uint32_t meta,
                                                 NeuronIn<RB>& in) {

@@ -23,6 +23,7 @@ constexpr int32_t PULL_TB_GATHER = 10;  // log2 neurons per pull tile, gather re
 constexpr int32_t SEL_LIGHT_RULES = 32;  // rules a thread scans alone; more: a wave per neuron
 constexpr int32_t BIN_TB = 12;          // log2 neurons per tile of the binned push
 constexpr int32_t BIN_MAX_TILES = 2048; // binned push up to 2048 tiles (8,388,608 neurons)
+constexpr int32_t PUSH_LIGHT = 32;      // wide push: row entries a thread walks alone
 
 // One rule of the rule vector RV in neuron order (16 bytes).
 //   Applicability of E = a^base (a^period)* together with n >= c is
@@ -96,6 +97,11 @@ struct SysDev {
   int32_t* bcnt[2];          // [bnb][bnb] records in region (b -> t), stored at [t][b], by k & 1
   const int32_t* boff;       // [bnb][bnb] first slot of region (b -> t), stored at [t][b]
   const int32_t* boffp;      // [bnb][bnb] the same, stored at [b][t]
+  // wide push: many-rule neurons choose by waves (hsel, heavy below); rows
+  // longer than PUSH_LIGHT entries are listed and walked by one wave each
+  int32_t push_wide;
+  int4* elist;               // [q] (neuron, rule slot, value sent, 0) of the listed emitters
+  int32_t* ecnt;             // [4] listed emitters of step k at ecnt[k % 3]
   // pull representation
   const int32_t* in_ptr;     // [q+1] in-neighbour lists (reads and counters)
   const int32_t* in_src;     // [nnz], each list in increasing source id
@@ -107,8 +113,8 @@ struct SysDev {
   int32_t pull_tb;           // log2 of the neurons per block (tile)
   int32_t pull_gather;       // 1: read emitted values from device memory (no LDS chunk)
   int32_t pull_wide;         // 1: wide schedule (reception and many-rule choices by waves)
-  int32_t* recv;             // wide: [q] spikes received at the step being executed
-  int32_t* hsel;             // wide: [q] rule slot chosen for a neuron with many rules
+  int32_t* recv;             // wide pull: [q] spikes received at the step being executed
+  int32_t* hsel;             // wide (pull or push): [q] rule slot chosen for a neuron with many rules
   const int32_t* heavy;      // wide: [n_heavy] neurons with more than SEL_LIGHT_RULES rules
   int32_t n_heavy;
   // bookkeeping
@@ -138,6 +144,7 @@ hipError_t launch_step_pull_batch_gather(const SysDev& s, const SysDev* members,
                                          const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                          hipStream_t st);
 hipError_t launch_step_push(const SysDev& s, int32_t j, hipStream_t st);
+hipError_t launch_step_push_wide(const SysDev& s, int32_t j, hipStream_t st);
 hipError_t launch_step_pull_batch(const SysDev& s, const SysDev* members, const int2* tiles,
                                   const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                   hipStream_t st);

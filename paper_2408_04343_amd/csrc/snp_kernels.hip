@@ -30,7 +30,8 @@ namespace snp {
 
 hipError_t launch_step(const SysDev& s, int32_t j, hipStream_t st) {
   if (s.layout == L_CSR_PULL) return launch_step_pull(s, j, st);
-  return s.push_binned ? launch_step_bin(s, j, st) : launch_step_push(s, j, st);
+  if (s.push_binned) return launch_step_bin(s, j, st);
+  return s.push_wide ? launch_step_push_wide(s, j, st) : launch_step_push(s, j, st);
 }
 
 hipError_t launch_step_batch(const SysDev& proto, const SysDev* members, const int2* tiles,

@@ -19,15 +19,6 @@ namespace snp {
 
 constexpr int WIDE_NT = 256;  // four waves per block, one target (or neuron) each
 
-// Would step k = k_base + j run?  (The same test as step_prologue, read-only.)
-__device__ __forceinline__ bool wide_runs(const SysDev& s, int32_t j, int64_t& k) {
-  const Ctl* ctl = s.ctl;
-  k = ctl->k_base + j;
-  if (ctl->halted || k >= ctl->k_limit) return false;
-  if (k > 0 && ctl->active[(k - 1) % 3] == 0) return false;
-  return true;
-}
-
 template <int W>
 __global__ void __launch_bounds__(WIDE_NT) recv_wide_kernel(SysDev s, int32_t j) {
   int64_t k;

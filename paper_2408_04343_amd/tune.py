@@ -1,7 +1,7 @@
 """Measured choice of the reception schedule of a system.
 
 `snp_create` picks a schedule from the system's shape alone (AUTO): staged,
-gather or wide pull; binned or atomic push.  The tuner instead builds the
+gather or wide pull; binned, atomic or wide push.  The tuner instead builds the
 system once per candidate schedule, runs a few steps of each on the GPU and
 keeps the fastest.  The candidates compute the same trajectory (tested bit
 for bit), so the choice only changes the speed.
@@ -13,7 +13,7 @@ import dataclasses
 from . import binding
 
 PULL_CANDIDATES = ("staged", "gather", "wide")
-PUSH_CANDIDATES = ("binned", "atomic")
+PUSH_CANDIDATES = ("binned", "atomic", "wide")
 
 
 @dataclasses.dataclass
@@ -34,7 +34,8 @@ def _mode_name(layout, info):
     if layout == "csr_pull":
         return {binding.PULL_STAGED: "staged", binding.PULL_GATHER: "gather",
                 binding.PULL_WIDE: "wide"}[info["pull_mode"]]
-    return {binding.PUSH_BINNED: "binned", binding.PUSH_ATOMIC: "atomic"}[info["push_mode"]]
+    return {binding.PUSH_BINNED: "binned", binding.PUSH_ATOMIC: "atomic",
+            binding.PUSH_WIDE: "wide"}[info["push_mode"]]
 
 
 def tune(spec, layout="csr_pull", steps=64, candidates=None, **kw) -> Choice:

@@ -60,15 +60,16 @@ def test_footprint_orders():
     dict(rules=[(2, 1, 0, 1, 1, 0)]),
     dict(pull_mode=4),
     dict(pull_mode=-1),
+    dict(push_mode=4),
 ])
 def test_invalid_systems_rejected_before_any_device_call(bad):
     from paper_2408_04343_amd import binding
-    kw = dict(q=2, s0=[1, 1], rules=[(0, 1, 0, 1, 1, 0)], src=[0], dst=[1], pull_mode=0)
+    kw = dict(q=2, s0=[1, 1], rules=[(0, 1, 0, 1, 1, 0)], src=[0], dst=[1], pull_mode=0, push_mode=0)
     kw.update(bad)
     s0 = kw["s0"] if kw["q"] == 2 else []
     with pytest.raises(binding.SnpError) as ei:
         binding.System(kw["q"], s0, kw["rules"], kw["src"], kw["dst"], memory="hip", stream=0,
-                       pull_mode=kw["pull_mode"])
+                       pull_mode=kw["pull_mode"], push_mode=kw["push_mode"])
     assert ei.value.status == -1
 
 

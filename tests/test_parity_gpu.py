@@ -15,10 +15,11 @@ pytestmark = pytest.mark.gpu
 # "csr_pull_gather" is the pull layout with its reception forced to read
 # emitted values from device memory (plain "csr_pull" stages them in LDS at
 # these sizes); the push layouts run binned at these sizes, "*_atomic" forces
-# device-wide atomic adds
+# device-wide atomic adds, "*_wide" the wide push schedule (waves choose
+# among many rules and walk long rows)
 LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "optimized_columns", "sliced", "ell",
            "ell_rows", "csr_push", "sparse", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic",
-           "sparse_atomic"]
+           "sparse_atomic", "optimized_wide", "sliced_wide", "ell_wide", "csr_push_wide", "sparse_wide"]
 
 
 def lk(layout):
@@ -27,6 +28,8 @@ def lk(layout):
         return {"layout": "csr_pull", "pull_mode": layout[len("csr_pull_"):]}
     if layout.endswith("_atomic"):
         return {"layout": layout[:-len("_atomic")], "push_mode": "atomic"}
+    if layout.endswith("_wide"):
+        return {"layout": layout[:-len("_wide")], "push_mode": "wide"}
     if layout == "ell_rows":   # ELL stored row by row (Table 2's drawing) instead of rule by rule
         return {"layout": "ell", "ell_rows": True}
     if layout == "optimized_columns":   # Sy stored neuron by neuron instead of row by row
@@ -125,16 +128,20 @@ def test_sort_family_closed_form(binding, layout):
         g.close()
 
 
-@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_pull_staged", "sliced", "ell"])
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_pull_staged", "sliced", "ell", "optimized",
+                                    "csr_push", "sparse", "ell_binned", "ell_atomic"])
 def test_sort_family_many_rules(binding, layout):
     # 700 rules on each sorting neuron: a wave scans them 64 at a time
     rng = np.random.default_rng(12)
     v = rng.integers(1, 400, size=700).tolist()
     spec = wl.sort_system(v)
-    kw = {"layout": "csr_pull", "pull_mode": "staged"} if layout == "csr_pull_staged" else lk(layout)
+    kw = {"layout": "csr_pull", "pull_mode": "staged"} if layout == "csr_pull_staged" else \
+        {"layout": "ell", "push_mode": "binned"} if layout == "ell_binned" else lk(layout)
     g = binding.System.from_spec(spec, **kw)
     if layout == "csr_pull":   # 735 K in-edges on one 4096-neuron tile: the wide schedule
         assert g.info()["pull_mode"] == binding.PULL_WIDE
+    if layout in ("sliced", "ell", "optimized", "csr_push", "sparse"):   # the same, pushed
+        assert g.info()["push_mode"] == binding.PUSH_WIDE
     g.step(10_000)
     assert g.steps_done() == (max(v) + 1, True)
     C = g.read_config()
@@ -577,6 +584,12 @@ def test_batch_rejects_wide_members(binding):
         binding.Batch([a])
     assert ei.value.status == -6
     a.step(3)
+    c = binding.System.from_spec(wl.small_random(1, 100), layout="ell", push_mode="wide")
+    assert c.info()["push_mode"] == binding.PUSH_WIDE
+    with pytest.raises(binding.SnpError) as ei:
+        binding.Batch([c])
+    assert ei.value.status == -6
+    c.step(3)
 
 
 def test_batch_rejects_mixed_members(binding):
