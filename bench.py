@@ -281,7 +281,7 @@ def run_skewed(binding, torch, steps=500, warmup=16,
     return out
 
 
-def run_sort(binding, torch, sizes=(100, 1000, 5000), layouts=("csr_pull", "sliced"), push_max_n=1000):
+def run_sort(binding, torch, sizes=(100, 1000, 5000), layouts=("csr_pull", "sliced"), push_max_n=5000):
     """The paper's sorting family (Sec. 6, Table 1): n inputs v ~ U{1..n},
     q = 3n neurons, n + n^2 rules (n on each sorting neuron), 1.5 n^2
     synapses; runs to halting (max(v) + 1 steps) and checks the closed form
