@@ -114,7 +114,9 @@ class DenseSystem:
             return False
         return not applicable_matrix(self.C, self.rules).any()
 
-    def step(self):
+    def step(self, choice=None):
+        """One step; `choice[i]` (optional) is the rule open neuron i uses
+        (one of its applicable rules, -1 when it has none)."""
         if self.halted():
             return False
         q, m = self.q, self.m
@@ -134,7 +136,12 @@ class DenseSystem:
             if not cand:
                 Dn[i] = 0
                 continue
-            r = cand[0] if self.sel == SEL_FIRST else cand[_choose(self.seed, self.k, i, len(cand))]
+            if choice is not None:
+                r = int(choice[i])
+                if r not in cand:
+                    raise ValueError("rule %d is not applicable in neuron %d" % (r, i))
+            else:
+                r = cand[0] if self.sel == SEL_FIRST else cand[_choose(self.seed, self.k, i, len(cand))]
             sel[r] = 1
             newS[i] = r
             d = int(self.rules[r, 5])

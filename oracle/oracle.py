@@ -101,6 +101,12 @@ def _load():
         lib.orc_build_sy.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
         lib.orc_set_synapses.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32)]
         lib.orc_set_synapses.restype = ct.c_int
+        lib.orc_set_state.argtypes = [ct.c_void_p, P(ct.c_int32), P(ct.c_int32), P(ct.c_int32)]
+        lib.orc_set_state.restype = ct.c_int
+        lib.orc_applicable.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
+        lib.orc_applicable.restype = ct.c_int32
+        lib.orc_step_choice.argtypes = [ct.c_void_p, P(ct.c_int32)]
+        lib.orc_step_choice.restype = ct.c_int
         _lib = lib
     return _lib
 
@@ -181,6 +187,52 @@ class OracleSystem:
         st = self._lib.orc_set_synapses(self._h, len(sa), _ip(sa), _ip(da))
         if st != 0:
             raise OracleError("orc_set_synapses failed with %d" % st)
+
+    def set_state(self, C, D, pend):
+        """Loads configuration (C, D, pend) (pend: rule waiting while closed, -1 none)."""
+        a = [np.ascontiguousarray(x, np.int32) for x in (C, D, pend)]
+        if any(x.shape != (self.q,) for x in a) or self._lib.orc_set_state(self._h, *map(_ip, a)) != 0:
+            raise OracleError("invalid configuration")
+
+    def applicable(self, i: int):
+        """Applicable rules of neuron i now, in increasing rule id ([] if closed)."""
+        out = np.empty(max(1, self.m), np.int32)
+        return out[:int(self._lib.orc_applicable(self._h, i, _ip(out)))].tolist()
+
+    def step_choice(self, choice) -> bool:
+        """One step in which open neuron i uses rule choice[i]; False if halted."""
+        ch = np.ascontiguousarray(choice, np.int32)
+        st = self._lib.orc_step_choice(self._h, _ip(ch))
+        if st < 0:
+            raise OracleError("a choice is not an applicable rule of its neuron")
+        return st == 1
+
+    def children(self, C, D, pend):
+        """Successors of configuration (C, D, pend) in the computation tree
+        (Sec. 2: every open neuron with applicable rules uses one of them).
+        One child per combination, enumerated in mixed radix: open neurons
+        with a choice in increasing id, neuron order least significant first,
+        each digit indexing the neuron's applicable rules in increasing id.
+        Returns a list of (C, D, pend); [] for a halted configuration."""
+        self.set_state(C, D, pend)
+        opts = [(i, self.applicable(i)) for i in range(self.q)]
+        opts = [(i, a) for i, a in opts if a]
+        total = 1
+        for _i, a in opts:
+            total *= len(a)
+        out = []
+        for x in range(total):
+            choice = np.full(self.q, -1, np.int32)
+            rest = x
+            for i, a in opts:
+                choice[i] = a[rest % len(a)]
+                rest //= len(a)
+            self.set_state(C, D, pend)
+            if not self.step_choice(choice):
+                return []          # halted: no successor
+            r = self.read()
+            out.append((r["C"], r["D"], r["pend"]))
+        return out
 
     def step_record(self, n: int, want_state=True):
         """Runs up to n steps; returns dict of per-step C, D, S [t, q], digests [t], counters."""

@@ -297,10 +297,26 @@ int orc_is_halted(const orc_sys* s) {
   return 1;
 }
 
-/* Executes one transition step.  Returns 1 if executed, 0 if halted. */
-static int step_once(orc_sys* s) {
+/* Executes one transition step.  Returns 1 if executed, 0 if halted, -1 if
+ * `choice` names a rule that is not applicable in its neuron.  choice NULL:
+ * the system's own choice (FIRST or HASH); otherwise choice[i] is the rule
+ * that open neuron i uses (one of its applicable rules, -1 when it has none). */
+static int step_with(orc_sys* s, const int32_t* choice) {
   if (s->halted) return 0;
   if (orc_is_halted(s)) { s->halted = 1; return 0; }
+  if (choice) {
+    /* a neuron with an applicable rule uses exactly one of them (Sec. 2) */
+    for (int32_t i = 0; i < s->q; ++i) {
+      if (s->D[i] != 0) continue;   /* closed: its entry is ignored */
+      int32_t want = choice[i], ok = 0, any = 0;
+      for (int32_t j = s->rstart[i]; j < s->rstart[i + 1]; ++j)
+        if (applicable(&s->rules[s->rlist[j]], s->C[i])) {
+          any = 1;
+          if (s->rlist[j] == want) ok = 1;
+        }
+      if (any ? !ok : want != -1) return -1;
+    }
+  }
   orc_counters c;
   memset(&c, 0, sizeof(c));
   const int32_t q = s->q;
@@ -319,7 +335,8 @@ static int step_once(orc_sys* s) {
         if (applicable(&s->rules[r], s->C[i])) s->cand[na++] = r;
       }
       if (na > 0) {
-        if (s->sel == ORC_SEL_FIRST) sel_rule = s->cand[0];
+        if (choice) sel_rule = choice[i];
+        else if (s->sel == ORC_SEL_FIRST) sel_rule = s->cand[0];
         else sel_rule = s->cand[orc_pick(orc_hash(s->seed, s->k, i), (uint32_t)na)];
       }
       if (sel_rule >= 0) {
@@ -387,12 +404,48 @@ static int step_once(orc_sys* s) {
   return 1;
 }
 
+static int step_once(orc_sys* s) { return step_with(s, NULL); }
+
 /* Runs up to n steps; returns the number executed (fewer if it halts). */
 int64_t orc_step(orc_sys* s, int64_t n) {
   int64_t done = 0;
   while (done < n && step_once(s)) done++;
   return done;
 }
+
+/* ---- branches of the computation (Sec. 2: a neuron with several applicable
+ * rules uses one of them, chosen nondeterministically; the SAMPLE_ONE step of
+ * Alg. 1 follows a single branch) ------------------------------------------ */
+
+/* Loads configuration (C, D, pend): pend[i] is the rule neuron i waits to
+ * fire while D[i] > 0 (STANDARD reading), else -1.  Returns -1 if invalid. */
+int orc_set_state(orc_sys* s, const int32_t* C, const int32_t* D, const int32_t* pend) {
+  for (int32_t i = 0; i < s->q; ++i) {
+    if (C[i] < 0 || D[i] < 0 || pend[i] < -1 || pend[i] >= s->m) return -1;
+    if (pend[i] >= 0 && s->rules[pend[i]].neuron != i) return -1;
+  }
+  for (int32_t i = 0; i < s->q; ++i) {
+    s->C[i] = C[i];
+    s->D[i] = D[i];
+    s->pend[i] = pend[i];
+    s->S[i] = -1;
+  }
+  s->halted = 0;
+  return 0;
+}
+
+/* Applicable rules of neuron i at its current count, in increasing rule id
+ * (none while the neuron is closed); returns how many were written. */
+int32_t orc_applicable(const orc_sys* s, int32_t i, int32_t* out) {
+  int32_t n = 0;
+  if (s->D[i] != 0) return 0;
+  for (int32_t j = s->rstart[i]; j < s->rstart[i + 1]; ++j)
+    if (applicable(&s->rules[s->rlist[j]], s->C[i])) out[n++] = s->rlist[j];
+  return n;
+}
+
+/* One step in which open neuron i uses rule choice[i]. */
+int orc_step_choice(orc_sys* s, const int32_t* choice) { return step_with(s, choice); }
 
 /* Like orc_step, but records C (clamped to int32 bits), D, S after every
  * executed step into row t of the [n][q] output arrays (any may be NULL) and

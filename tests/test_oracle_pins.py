@@ -347,6 +347,99 @@ def test_selection_is_a_valid_spiking_vector():
                                       [sorted({s[i] for s in valid}) for i in range(spec.q)])
 
 
+# ---------------------------------------------------- computation tree ----
+
+def _child_tuples(ch):
+    return [(c.tolist(), d.tolist(), p.tolist()) for c, d, p in ch]
+
+
+def test_tree_hand_examples():
+    # one neuron with 4 spikes and rules r0 = a^3 (c 3), r1 = a^2(a^2)* (c 2),
+    # r2 = a(a)* (c 1), r3 = a^4 (c 4): r1, r2 and r3 apply, r0 does not;
+    # using one of them consumes 2, 1 or 4 spikes, so the children hold 2, 3, 0
+    rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
+    o = orc.OracleSystem(1, [4], rules, [], [])
+    assert _child_tuples(o.children([4], [0], [-1])) == [([2], [0], [-1]), ([3], [0], [-1]), ([0], [0], [-1])]
+    # with no spike no rule applies: halted, no children; a closed neuron
+    # (r2 pending) has no choice: one child, reopened
+    assert o.children([0], [0], [-1]) == []
+    assert _child_tuples(o.children([0], [1], [2])) == [([0], [0], [-1])]
+    # sigma0 -> sigma1, sigma0 holds 2 spikes, r0 = a^2 -> a (delay 0), r1 =
+    # a(a)*/a -> a; 1.  r0 sends its spike at once: (0, 1).  Under the standard
+    # reading r1 consumes one spike and closes sigma0 for one step with r1
+    # pending: C (1, 0), D (1, 0); at the next step sigma0 reopens and its
+    # spike reaches sigma1: (1, 1), all open.  Read as the kernels print it,
+    # r1's spike leaves at selection: C (1, 1), D (1, 0); then nothing moves.
+    rules = [(0, 2, 0, 2, 1, 0), (0, 1, 1, 1, 1, 1)]
+    o = orc.OracleSystem(2, [2, 0], rules, [0], [1], STD)
+    ch = o.children([2, 0], [0, 0], [-1, -1])
+    assert _child_tuples(ch) == [([0, 1], [0, 0], [-1, -1]), ([1, 0], [1, 0], [1, -1])]
+    assert _child_tuples(o.children(*ch[1])) == [([1, 1], [0, 0], [-1, -1])]
+    o = orc.OracleSystem(2, [2, 0], rules, [0], [1], PK)
+    ch = o.children([2, 0], [0, 0], [-1, -1])
+    assert _child_tuples(ch) == [([0, 1], [0, 0], [-1, -1]), ([1, 1], [1, 0], [-1, -1])]
+    assert _child_tuples(o.children(*ch[1])) == [([1, 1], [0, 0], [-1, -1])]
+
+
+def _tree_walk(o, spec, depth):
+    """Configurations reached by every branch up to `depth` steps (with repeats)."""
+    level = [(np.array(spec.spikes0, np.int32), np.zeros(spec.q, np.int32), np.full(spec.q, -1, np.int32))]
+    for _ in range(depth):
+        nxt = []
+        for node in level[:40]:
+            nxt.extend(o.children(*node))
+        yield level
+        level = nxt
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_tree_children_are_every_valid_spiking_vector(sem):
+    # the children are exactly the dense-matrix steps (C' = C + S M with the
+    # delay masks) over every valid spiking vector, and there are as many as
+    # the product of the open neurons' numbers of applicable rules
+    branching = 0
+    for t in range(40):
+        spec = wl.small_random(4000 + t, 4, max_deg=3, max_rules=3, dmax=2, c0max=5)
+        o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, sem)
+        for level in _tree_walk(o, spec, 4):
+            for C, D, P in level[:10]:
+                ch = o.children(C, D, P)
+                valid = _valid_spiking_vectors(C, D, spec.rules.tolist(), spec.q)
+                want = set()
+                d = dense.DenseSystem(spec.q, C, spec.rules, list(zip(spec.src, spec.dst)), sem)
+                halted = (not np.any(D)) and valid == {tuple([-1] * spec.q)}
+                for S in valid:
+                    d.C, d.D, d.pend = np.array(C, np.int64), np.array(D, np.int64), np.array(P, np.int64)
+                    if d.step(S):
+                        want.add((tuple(d.C.tolist()), tuple(d.D.tolist()), tuple(d.pend.tolist())))
+                got = {(tuple(c.tolist()), tuple(x.tolist()), tuple(p.tolist())) for c, x, p in ch}
+                assert got == want, (t, C, D, P)
+                # one child per valid spiking vector, none when halted
+                assert len(ch) == (0 if halted else len(valid))
+                branching = max(branching, len(ch))
+    assert branching >= 4
+
+
+def test_tree_contains_the_first_and_hash_branches():
+    for t in range(40):
+        spec = wl.small_random(5000 + t, 5, max_deg=3, max_rules=3, dmax=2, c0max=5)
+        o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, STD)
+        root = (spec.spikes0, np.zeros(spec.q, np.int32), np.full(spec.q, -1, np.int32))
+        ch = _child_tuples(o.children(*root))
+        f = make(spec, STD, FIRST)
+        if f.step(1):
+            r = f.read()
+            # all digits 0: every neuron takes its lowest applicable rule
+            assert ch[0] == (r["C"].tolist(), r["D"].tolist(), r["pend"].tolist())
+            for seed in range(5):
+                h = make(spec, STD, HASH, seed)
+                h.step(1)
+                r = h.read()
+                assert (r["C"].tolist(), r["D"].tolist(), r["pend"].tolist()) in ch
+        else:
+            assert ch == []
+
+
 # ---------------------------------------------------------- invariants ----
 
 def _conservation_check(spec, sem, sel, steps):
