@@ -278,6 +278,33 @@ int snp_write_state(snp_sys* sys, const int32_t* config, const int32_t* delays,
  * handle in a batch or sharing its representation with clones.            */
 int snp_set_synapses(snp_sys* sys, int64_t nsyn, const int32_t* syn_src, const int32_t* syn_dst);
 
+/* Branches of the computation (Sec. 2: an open neuron with several
+ * applicable rules uses one of them, chosen nondeterministically; SAMPLE_ONE
+ * in Alg. 1 follows a single branch).  For each of `nstates` configurations
+ * of the system (host buffers [nstates][q]: spike counts C >= 0, delay
+ * counters D >= 0, pending rule ids as snp_read_pending gives them: under
+ * SNP_SEM_STANDARD a closed neuron's waiting rule and -1 exactly for open
+ * neurons, under SNP_SEM_PAPER_KERNEL always -1) every successor is
+ * written: one per combination of one applicable rule for each open neuron
+ * that has one, none for a halted configuration (every neuron open and no
+ * rule applicable).  Successors of configuration x come before those of
+ * x + 1; within x, combination j takes for the open neurons with a choice,
+ * in increasing neuron id, the digits of j in mixed radix (the first such
+ * neuron the least significant), digit = index among the neuron's applicable
+ * rules in increasing rule id.  The system's own state, choice mode and
+ * step counter are not used or changed.
+ * Outputs (host): child_C, child_D, child_pend [cap][q] and child_parent
+ * [cap] (index of the configuration each successor comes from);
+ * *nchildren = the number of successors.  With any output NULL only
+ * *nchildren is set (a size query); cap < *nchildren is SNP_EINVAL.  More
+ * than 2^31 successors: SNP_ENOTSUP; a successor count beyond int32:
+ * SNP_EOVERFLOW.  Synchronous (returns when the outputs are written); meant
+ * for small systems (each successor costs O(q + rules + synapses) on one
+ * GPU thread). */
+int snp_expand(snp_sys* sys, int32_t nstates, const int32_t* C, const int32_t* D, const int32_t* pend,
+               int64_t cap, int32_t* child_C, int32_t* child_D, int32_t* child_pend, int32_t* child_parent,
+               int64_t* nchildren);
+
 /* Device copy of the representation, for inspection (host buffers):
  *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
  *   which = SNP_LAYOUT_SLICED: the slices expanded to the same [z][q] Sy;

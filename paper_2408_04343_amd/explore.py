@@ -1,11 +1,17 @@
-"""Sampling the computation tree of a system with many choice keys at once.
+"""The computation tree of a system: sampled branches and full levels.
 
 An SNP system is nondeterministic where a neuron has several applicable rules
 (Sec. 2); the paper simulates one branch of the computation per run (its
-SAMPLE_ONE step).  Here each sample is a clone of the system (shared rules
-and synapses, own state) with its own HASH key, and all samples advance in
-one batch, one launch per step: a sample's branch is the one the HASH choice
-with its key takes, identical to a run of that key alone.
+SAMPLE_ONE step).
+
+`explore` samples branches: each sample is a clone of the system (shared
+rules and synapses, own state) with its own HASH key, and all samples advance
+in one batch, one launch per step: a sample's branch is the one the HASH
+choice with its key takes, identical to a run of that key alone.
+
+`tree` enumerates the levels of the tree of a small system: level k + 1 holds
+every successor (`snp_expand`, one GPU thread per successor) of the
+configurations of level k.
 """
 from __future__ import annotations
 
@@ -42,3 +48,32 @@ def explore(system: "binding.System", seeds, steps: int, spikes0=None, chunk: in
         out["digest"][x] = g.digest()
         g.close()
     return out
+
+
+def tree(system: "binding.System", spikes0, depth: int, merge: bool = True, max_nodes: int = 1 << 20):
+    """Levels 0..depth of the computation tree from C_0 = `spikes0` (every
+    neuron open, nothing pending).  With `merge`
+    identical configurations of a level are kept once (the configuration
+    graph; the first parent is kept).  Returns a list of dicts with arrays
+    C, D, pend [n, q] and parent [n] (index into the previous level, -1 at
+    level 0); stops early at a level with no configuration, and raises if a
+    level would exceed `max_nodes`."""
+    q = system.q
+    C0 = np.asarray(spikes0, np.int32).reshape(1, q)
+    level = {"C": C0.copy(), "D": np.zeros((1, q), np.int32), "pend": np.full((1, q), -1, np.int32),
+             "parent": np.full(1, -1, np.int32)}
+    levels = [level]
+    for _ in range(depth):
+        nxt = system.expand(level["C"], level["D"], level["pend"])
+        if len(nxt["parent"]) > max_nodes:
+            raise RuntimeError("level of %d configurations exceeds max_nodes" % len(nxt["parent"]))
+        if merge and len(nxt["parent"]):
+            key = np.concatenate([nxt["C"], nxt["D"], nxt["pend"]], axis=1)
+            _u, first = np.unique(key, axis=0, return_index=True)
+            keep = np.sort(first)
+            nxt = {k: v[keep] for k, v in nxt.items()}
+        levels.append(nxt)
+        if len(nxt["parent"]) == 0:
+            break
+        level = nxt
+    return levels

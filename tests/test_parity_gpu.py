@@ -716,3 +716,108 @@ def test_served_results_equal_alone(binding):
                              req.seed)
         n = o.step(req.steps)
         assert results[req.rid] == (n, o.digest()), req.rid
+
+
+# ------------------------------------------------------- computation tree ----
+
+def _oracle_levels(o, spikes0, depth):
+    level = [(np.asarray(spikes0, np.int32), np.zeros(o.q, np.int32), np.full(o.q, -1, np.int32))]
+    out = [level]
+    for _ in range(depth):
+        nxt, seen = [], set()
+        for node in level:
+            for ch in o.children(*node):
+                key = tuple(np.concatenate(ch).tolist())
+                if key not in seen:
+                    seen.add(key)
+                    nxt.append(ch)
+        out.append(nxt)
+        if not nxt:
+            break
+        level = nxt
+    return out
+
+
+@pytest.mark.parametrize("sem_name,sem", SEMS)
+def test_expand_equals_oracle_children(binding, sem_name, sem):
+    # every successor, in the same order, for configurations reached along
+    # the tree of small random systems with branching and delays
+    branching = 0
+    for t in range(30):
+        spec = wl.small_random(6000 + t, 6, max_deg=3, max_rules=3, dmax=2, c0max=5)
+        o = oracle_of(spec, sem)
+        g = binding.System.from_spec(spec, layout="csr_pull", semantics=sem_name)
+        level = [(spec.spikes0.astype(np.int32), np.zeros(spec.q, np.int32), np.full(spec.q, -1, np.int32))]
+        for _depth in range(4):
+            nodes = level[:12]
+            got = g.expand(np.stack([x[0] for x in nodes]), np.stack([x[1] for x in nodes]),
+                           np.stack([x[2] for x in nodes]))
+            want, parents = [], []
+            for j, node in enumerate(nodes):
+                ch = o.children(*node)
+                want.extend(ch)
+                parents.extend([j] * len(ch))
+            assert len(got["parent"]) == len(want), (t, _depth)
+            assert got["parent"].tolist() == parents
+            for x, (c, d, p) in enumerate(want):
+                assert got["C"][x].tolist() == c.tolist(), (t, _depth, x)
+                assert got["D"][x].tolist() == d.tolist()
+                assert got["pend"][x].tolist() == p.tolist()
+            branching = max(branching, max([parents.count(j) for j in range(len(nodes))] + [0]))
+            level = want
+            if not level:
+                break
+    assert branching >= 4
+
+
+@pytest.mark.parametrize("layout", ["csr_pull", "ell", "sparse"])
+def test_tree_levels_equal_oracle(binding, layout):
+    from paper_2408_04343_amd import explore
+    spec = wl.small_random(77, 7, max_deg=3, max_rules=3, dmax=2, c0max=6)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    g = binding.System.from_spec(spec, layout=layout)
+    levels = explore.tree(g, spec.spikes0, 6)
+    ref = _oracle_levels(o, spec.spikes0, 6)
+    assert len(levels) == len(ref)
+    for lv, rf in zip(levels, ref):
+        got = {tuple(np.concatenate([lv["C"][x], lv["D"][x], lv["pend"][x]]).tolist())
+               for x in range(len(lv["C"]))}
+        want = {tuple(np.concatenate(ch).tolist()) for ch in rf}
+        assert got == want
+    # the system's own trajectory is one branch of the tree
+    g.step(3)
+    node = tuple(np.concatenate([g.read_config(), g.read_delays(), g.read_pending()]).tolist())
+    lv = levels[3]
+    assert node in {tuple(np.concatenate([lv["C"][x], lv["D"][x], lv["pend"][x]]).tolist())
+                    for x in range(len(lv["C"]))}
+
+
+def test_expand_hand_examples_and_limits(binding):
+    rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
+    g = binding.System(1, [4], rules, [], [])
+    r = g.expand([4], [0], [-1])
+    assert r["C"].ravel().tolist() == [2, 3, 0] and r["parent"].tolist() == [0, 0, 0]
+    assert len(g.expand([0], [0], [-1])["parent"]) == 0            # halted
+    # sorting family: one rule applies per neuron, so the tree is a path equal to the run
+    from paper_2408_04343_amd import explore
+    spec = wl.sort_system([3, 1, 2])
+    s = binding.System.from_spec(spec)
+    levels = explore.tree(s, spec.spikes0, 10)
+    assert [len(lv["parent"]) for lv in levels] == [1, 1, 1, 1, 1, 0]
+    assert levels[4]["C"][0].tolist() == [0] * 6 + [1, 2, 3]
+    # bad configurations are rejected before any device work
+    for bad in (([-1], [0], [-1]), ([4], [1], [-1]), ([4], [0], [2]), ([4], [0], [9])):
+        with pytest.raises(binding.SnpError) as ei:
+            g.expand(*bad)
+        assert ei.value.status == -1
+    # a buffer smaller than the successors is rejected
+    import ctypes as ct
+    n = ct.c_int64()
+    C = np.array([4], np.int32)
+    Z = np.zeros(1, np.int32)
+    P = np.full(1, -1, np.int32)
+    small = np.zeros(2, np.int32)
+    st = binding.lib.snp_expand(g._h, 1, binding._ptr(C), binding._ptr(Z), binding._ptr(P), 2,
+                                binding._ptr(small), binding._ptr(small), binding._ptr(small),
+                                binding._ptr(small), ct.byref(n))
+    assert st == -1 and n.value == 3
