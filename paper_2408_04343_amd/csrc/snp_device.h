@@ -76,12 +76,12 @@ template <int RB>
 constexpr int kPrefetch = RB == 8 ? 4 : 2;
 
 __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
-  if (r.period == 0) return n == r.lo;
-  if (n < r.lo) return false;
   const uint32_t d = (uint32_t)(n - r.lo), per = (uint32_t)r.period;
-  // a power-of-two period (1, 2, 4, ...) needs no division
-  if ((per & (per - 1u)) == 0u) return (d & (per - 1u)) == 0u;
-  return d % per == 0u;
+  const bool ge = n >= r.lo;
+  // period 0 (exactly lo: per - 1 has every bit set) and power-of-two
+  // periods (1, 2, 4, ...) are a mask test; only other periods divide
+  if ((per & (per - 1u)) == 0u) return ge & ((d & (per - 1u)) == 0u);
+  return ge & (d % per == 0u);
 }
 
 // What a neuron needs to take its step, loaded ahead of its use.  The rule
@@ -111,28 +111,35 @@ __device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64
                                                const NeuronIn<RB>& in) {
   constexpr int PF = kPrefetch<RB>;
   const int32_t n = in.C, r0 = in.r0, r1 = in.r1;
-#define SNP_APPLIES(X) (X < PF && r0 + X < r1 && rule_applies(decode(pf_at<X, RB>(in)), n))
+  // the prefetched records are tested without branches (a record past r1
+  // is a valid stand-in whose result is masked off)
+#define SNP_APPLIES(X) ((X < PF) & (r0 + X < r1) & rule_applies(decode(pf_at<X, RB>(in)), n))
+  const bool a0 = SNP_APPLIES(0), a1 = SNP_APPLIES(1), a2 = SNP_APPLIES(2), a3 = SNP_APPLIES(3);
+#undef SNP_APPLIES
   if (s.sel == SEL_FIRST) {
-    if (SNP_APPLIES(0)) return r0;
-    if (SNP_APPLIES(1)) return r0 + 1;
-    if (SNP_APPLIES(2)) return r0 + 2;
-    if (SNP_APPLIES(3)) return r0 + 3;
+    const uint32_t hit = (uint32_t)a0 | ((uint32_t)a1 << 1) | ((uint32_t)a2 << 2) | ((uint32_t)a3 << 3);
+    if (hit) return r0 + (int32_t)__builtin_ctz(hit);
     for (int32_t r = r0 + PF; r < r1; ++r)
       if (rule_applies(load_rule<RB>(s, r), n)) return r;
     return -1;
   }
-  const bool a0 = SNP_APPLIES(0), a1 = SNP_APPLIES(1), a2 = SNP_APPLIES(2), a3 = SNP_APPLIES(3);
-#undef SNP_APPLIES
-  uint32_t cnt = (uint32_t)a0 + (uint32_t)a1 + (uint32_t)a2 + (uint32_t)a3;
+  const uint32_t hit = (uint32_t)a0 | ((uint32_t)a1 << 1) | ((uint32_t)a2 << 2) | ((uint32_t)a3 << 3);
+  const uint32_t ph = (uint32_t)__builtin_popcount(hit);
+  uint32_t cnt = ph;
   for (int32_t r = r0 + PF; r < r1; ++r) cnt += rule_applies(load_rule<RB>(s, r), n) ? 1u : 0u;
   if (cnt == 0) return -1;
   const uint64_t key = ((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)i;
   const uint64_t h = mix64(mix64(s.seed) ^ key);
   uint32_t j = (uint32_t)(((h >> 32) * (uint64_t)cnt) >> 32);
-  if (a0) { if (j == 0) return r0; --j; }
-  if (a1) { if (j == 0) return r0 + 1; --j; }
-  if (a2) { if (j == 0) return r0 + 2; --j; }
-  if (a3) { if (j == 0) return r0 + 3; --j; }
+  if (j < ph) {
+    // the j-th set bit of hit: its j lower set bits cleared first
+    uint32_t m = hit;
+    m = j > 0 ? m & (m - 1u) : m;
+    m = j > 1 ? m & (m - 1u) : m;
+    m = j > 2 ? m & (m - 1u) : m;
+    return r0 + (int32_t)__builtin_ctz(m);
+  }
+  j -= ph;
   for (int32_t r = r0 + PF; r < r1; ++r) {
     if (rule_applies(load_rule<RB>(s, r), n)) {
       if (j == 0) return r;
