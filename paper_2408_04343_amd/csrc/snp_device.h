@@ -267,49 +267,45 @@ template <int RB, bool CNT>
 __device__ __forceinline__ Sel select_update(const SysDev& s, int32_t i, int64_t k,
                                              const NeuronIn<RB>& in, Cnt& cnt,
                                              int32_t chosen = CHOOSE_HERE) {
+  constexpr int PF = kPrefetch<RB>;
   const int32_t D = (int32_t)(in.meta & META_D);
-  int32_t Dn = 0, cons = 0, sel = -1;
-  Sel o{0, -1, false};
-  if (D == 0) {
-    sel = chosen == CHOOSE_HERE ? choose_rule<RB>(s, i, k, in) : chosen;
-    if (CNT) {
+  const bool open = D == 0;
+  int32_t sel = -1;
+  if (open) sel = chosen == CHOOSE_HERE ? choose_rule<RB>(s, i, k, in) : chosen;
+  const bool fired = sel >= 0;
+  // the record that matters: the selected rule's (open) or the pending
+  // rule's, which a closed neuron holds in p0; x < 0 when nothing fired
+  const int32_t x = sel - in.r0;
+  RawRule<RB> raw = in.p0;
+  raw = x == 1 ? in.p1 : raw;
+  if constexpr (PF > 2) {
+    raw = x == 2 ? in.p2 : raw;
+    raw = x == 3 ? in.p3 : raw;
+  }
+  Rule r = decode(raw);
+  if (fired && x >= PF) r = load_rule<RB>(s, sel);
+  const bool now = fired && (s.sem == SEM_PAPER || r.d == 0);          // spikes leave at selection
+  const int32_t Dn = open ? (fired ? r.d : 0) : D - 1;
+  const bool reopen = !open && s.sem == SEM_STANDARD && Dn == 0;      // the pending rule's spikes leave
+  Sel o;
+  o.emit = (now || reopen) ? r.p : 0;
+  o.erule = now ? sel : reopen ? in.pend : -1;
+  o.act = !open || fired;
+  if (fired && !now) s.pend[i] = sel;
+  if (CNT) {
+    if (open) {
       cnt.v[C_OPEN] += 1;
       cnt.v[C_RULES] += (unsigned long long)(in.r1 - in.r0);
     }
-    if (sel >= 0) {
-      const int32_t x = sel - in.r0;
-      const Rule r = x == 0 ? decode(in.p0)
-                   : x == 1 ? decode(in.p1)
-                   : (x == 2 && kPrefetch<RB> > 2) ? decode(in.p2)
-                   : (x == 3 && kPrefetch<RB> > 3) ? decode(in.p3)
-                   : load_rule<RB>(s, sel);
-      const int32_t rc = r.c, rp = r.p, rd = r.d;
-      cons = rc;
-      Dn = rd;
-      if (s.sem == SEM_PAPER || rd == 0) {
-        o.emit = rp;
-        o.erule = sel;
-      } else {
-        s.pend[i] = sel;
-      }
-      o.act = true;
-      if (CNT) cnt.v[C_SEL] += 1;
-    }
-  } else {
-    Dn = D - 1;
-    o.act = true;
-    if (CNT && Dn == 0) cnt.v[C_REOPEN] += 1;
-    if (s.sem == SEM_STANDARD && Dn == 0) {
-      o.erule = in.pend;
-      o.emit = decode(in.p0).p;
-    }
+    if (fired) cnt.v[C_SEL] += 1;
+    if (!open && Dn == 0) cnt.v[C_REOPEN] += 1;
+    if (o.emit > 0) cnt.v[C_EMIT] += 1;
   }
-  const uint32_t rf = (s.sem == SEM_PAPER) ? (D == 0 ? 1u : 0u) : (Dn == 0 ? 1u : 0u);
-  s.C[i] = in.C - cons;
+  const uint32_t rf = (s.sem == SEM_PAPER) ? (open ? 1u : 0u) : (Dn == 0 ? 1u : 0u);
+  s.C[i] = in.C - (fired ? r.c : 0);
   const uint32_t nm = (uint32_t)Dn | (rf << 31);
   if (nm != in.meta) s.meta[i] = nm;
-  pick(s.S16[0], s.S16[1], k)[i] = sel >= 0 ? (uint16_t)(sel - in.r0) : S_NONE;
-  if (CNT && o.emit > 0) cnt.v[C_EMIT] += 1;
+  pick(s.S16[0], s.S16[1], k)[i] = fired ? (uint16_t)x : S_NONE;
   return o;
 }
 
