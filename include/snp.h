@@ -130,6 +130,7 @@ extern "C" {
 #define SNP_F_COUNTERS 0x2u /* keep per-step work counters                   */
 #define SNP_F_NO_GRAPH 0x4u /* launch step kernels one by one (no hipGraph)  */
 #define SNP_F_WIDE_RULES 0x8u /* keep 16-byte rule records even when 8 fit  */
+#define SNP_F_RULES8   0x40u /* keep 8-byte rule records even when 4 fit    */
 #define SNP_F_SY_COLUMNS 0x20u /* Optimized Sy stored neuron by neuron ([q][z]:
                                  a neuron's column contiguous, read 16 bytes at
                                  a time) instead of row by row as Table 3 is

@@ -582,15 +582,34 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     int32_t* p;
     if ((st = upload(s, &p, rs.data(), rs.size())) != SNP_OK) return bail(st);
     d.rs = p;
-    // packed 8-byte records when every rule fits them
+    // packed 4- or 8-byte records when every rule fits them
     bool fits8 = !(o.flags & SNP_F_WIDE_RULES);
+    bool fits4 = fits8 && !(o.flags & SNP_F_RULES8);
+    for (int32_t x = 0; x < m && fits4; ++x) {
+      const RuleRec& R = rec[x];
+      const bool dead = R.period == 0 && R.lo < 0;
+      fits4 = (dead || (R.lo >= 0 && R.lo < 1023 && R.period < (int32_t)R4_DEAD)) && R.c < 256 &&
+              (R.pd & 0xFFFFu) < 16u && (R.pd >> 16) < 16u;
+    }
     for (int32_t x = 0; x < m && fits8; ++x) {
       const RuleRec& R = rec[x];
       const bool dead = R.period == 0 && R.lo < 0;
       fits8 = (dead || (R.lo >= 0 && R.lo < (1 << 24) && R.period < (int32_t)R8_DEAD)) && R.c < (1 << 16) &&
               (R.pd & 0xFFFFu) < 256u && (R.pd >> 16) < 256u;
     }
-    if (fits8) {
+    if (fits4) {
+      std::vector<uint32_t> r4((size_t)std::max(m, 1));
+      for (int32_t x = 0; x < m; ++x) {
+        const RuleRec& R = rec[x];
+        const bool dead = R.period == 0 && R.lo < 0;
+        r4[x] = (dead ? (R4_DEAD << 10) : ((uint32_t)R.lo | ((uint32_t)R.period << 10))) |
+                ((uint32_t)R.c << 16) | ((R.pd & 0xFu) << 24) | ((R.pd >> 16) << 28);
+      }
+      uint32_t* rp;
+      if ((st = upload(s, &rp, r4.data(), (size_t)m)) != SNP_OK) return bail(st);
+      d.rules4 = rp;
+      d.rule_bytes = 4;
+    } else if (fits8) {
       std::vector<uint2> r8((size_t)std::max(m, 1));
       for (int32_t x = 0; x < m; ++x) {
         const RuleRec& R = rec[x];

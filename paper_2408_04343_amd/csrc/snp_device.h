@@ -43,6 +43,10 @@ template <>
 struct RawRule<16> {
   RuleRec w;
 };
+template <>
+struct RawRule<4> {
+  uint32_t w;
+};
 
 template <int RB>
 __device__ __forceinline__ RawRule<RB> load_raw(const SysDev& s, int32_t slot);
@@ -53,6 +57,10 @@ __device__ __forceinline__ RawRule<8> load_raw<8>(const SysDev& s, int32_t slot)
 template <>
 __device__ __forceinline__ RawRule<16> load_raw<16>(const SysDev& s, int32_t slot) {
   return RawRule<16>{s.rules[slot]};
+}
+template <>
+__device__ __forceinline__ RawRule<4> load_raw<4>(const SysDev& s, int32_t slot) {
+  return RawRule<4>{s.rules4[slot]};
 }
 
 __device__ __forceinline__ Rule decode(const RawRule<16>& y) {
@@ -66,6 +74,12 @@ __device__ __forceinline__ Rule decode(const RawRule<8>& y) {
               (int32_t)(x.y & 0xFFFFu), (int32_t)((x.y >> 16) & 0xFFu), (int32_t)(x.y >> 24)};
 }
 
+__device__ __forceinline__ Rule decode(const RawRule<4>& y) {
+  const uint32_t x = y.w, per = (x >> 10) & 0x3Fu;
+  return Rule{per == R4_DEAD ? -1 : (int32_t)(x & 0x3FFu), per == R4_DEAD ? 0 : (int32_t)per,
+              (int32_t)((x >> 16) & 0xFFu), (int32_t)((x >> 24) & 0xFu), (int32_t)(x >> 28)};
+}
+
 template <int RB>
 __device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
   return decode(load_raw<RB>(s, slot));
@@ -73,7 +87,7 @@ __device__ __forceinline__ Rule load_rule(const SysDev& s, int32_t slot) {
 
 // Rule records of one neuron kept in registers before its selection.
 template <int RB>
-constexpr int kPrefetch = RB == 8 ? 4 : 2;
+constexpr int kPrefetch = RB == 16 ? 2 : 4;
 
 __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   const uint32_t d = (uint32_t)(n - r.lo), per = (uint32_t)r.period;

@@ -44,6 +44,12 @@ struct RuleRec {
 //   y = c | p << 16 | d << 24
 constexpr uint32_t R8_DEAD = 0xFFu;
 
+// Packed 4-byte record, used when every rule has lo < 1023, period < 63,
+// c < 256, p < 16 and d < 16:
+//   x = lo | period << 10 | c << 16 | p << 24 | d << 28
+//   (period field R4_DEAD: the rule never applies)
+constexpr uint32_t R4_DEAD = 0x3Fu;
+
 // Control block of one system, in device memory.
 struct Ctl {
   int64_t k_base;     // system-local index of launch 0 of the current run of launches
@@ -69,10 +75,11 @@ struct SysDev {
   uint16_t* S16[2];          // local index of the rule selected at step k (k & 1)
   // rule vector, neuron-rule map
   const int32_t* rs;         // [q+1] rules of neuron i: slots rs[i] .. rs[i+1]-1
-  int32_t rule_bytes;        // 8: rules8 holds the rule vector, 16: rules does
+  int32_t rule_bytes;        // 4: rules4 holds the rule vector, 8: rules8, 16: rules
   int32_t sel_wave;          // 1: some neuron has more rules than a thread scans alone
   const RuleRec* rules;      // [m] in slot order
   const uint2* rules8;       // [m] in slot order, packed
+  const uint32_t* rules4;    // [m] in slot order, packed into 4 bytes
   const int32_t* rid;        // [m] caller id of each slot
   // push representations
   int32_t* delta[2];         // spikes received at step k, by k & 1

@@ -181,7 +181,8 @@ __global__ void activity_kernel(SysDev s, const int32_t* C, const int32_t* D, in
 
 hipError_t launch_activity(const SysDev& s, const int32_t* C, const int32_t* D, int32_t* out,
                            hipStream_t st) {
-  if (s.rule_bytes == 8) activity_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
+  if (s.rule_bytes == 4) activity_kernel<4><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
+  else if (s.rule_bytes == 8) activity_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
   else activity_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, C, D, out);
   return hipGetLastError();
 }
@@ -267,7 +268,8 @@ __global__ void build_dense_kernel(SysDev s, int32_t* dense) {
 }
 
 hipError_t launch_build_dense(const SysDev& s, int32_t* dense, hipStream_t st) {
-  if (s.rule_bytes == 8) build_dense_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
+  if (s.rule_bytes == 4) build_dense_kernel<4><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
+  else if (s.rule_bytes == 8) build_dense_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
   else build_dense_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, dense);
   return hipGetLastError();
 }
@@ -296,7 +298,8 @@ __global__ void build_ell_kernel(SysDev s, int2* ell) {
 }
 
 hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st) {
-  if (s.rule_bytes == 8) build_ell_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
+  if (s.rule_bytes == 4) build_ell_kernel<4><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
+  else if (s.rule_bytes == 8) build_ell_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
   else build_ell_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
   return hipGetLastError();
 }

@@ -538,6 +538,9 @@ static hipError_t launch_bin_batch_rf(const SysDev& s, const SysDev* members, co
 
 hipError_t launch_step_bin(const SysDev& s, int32_t j, hipStream_t st) {
   if (s.bnb > BIN_MAX_TILES) return hipErrorInvalidValue;
+  if (s.rule_bytes == 4) {
+    SNP_FLAGS_DISPATCH(launch_bin_rf, 4, s, j, st)
+  }
   if (s.rule_bytes == 8) {
     SNP_FLAGS_DISPATCH(launch_bin_rf, 8, s, j, st)
   }
@@ -547,6 +550,9 @@ hipError_t launch_step_bin(const SysDev& s, int32_t j, hipStream_t st) {
 hipError_t launch_step_bin_batch(const SysDev& s, const SysDev* members, const int2* tiles,
                                  const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                  hipStream_t st) {
+  if (s.rule_bytes == 4) {
+    SNP_FLAGS_DISPATCH(launch_bin_batch_rf, 4, s, members, tiles, ntiles, grid, lds, j, st)
+  }
   if (s.rule_bytes == 8) {
     SNP_FLAGS_DISPATCH(launch_bin_batch_rf, 8, s, members, tiles, ntiles, grid, lds, j, st)
   }

@@ -326,6 +326,9 @@ static hipError_t launch_pull_batch_rf(const SysDev& s, const SysDev* members, c
 
 template <int TB, int G>
 static hipError_t launch_pull_mode(const SysDev& s, int32_t j, hipStream_t st) {
+  if (s.rule_bytes == 4) {
+    SNP_FLAGS_DISPATCH(launch_pull_rf, 4, s, j, st)
+  }
   if (s.rule_bytes == 8) {
     SNP_FLAGS_DISPATCH(launch_pull_rf, 8, s, j, st)
   }
@@ -336,6 +339,9 @@ template <int TB, int G>
 static hipError_t launch_pull_batch_mode(const SysDev& s, const SysDev* members, const int2* tiles,
                                          const int32_t* ntiles, int32_t grid, size_t lds, int32_t j,
                                          hipStream_t st) {
+  if (s.rule_bytes == 4) {
+    SNP_FLAGS_DISPATCH(launch_pull_batch_rf, 4, s, members, tiles, ntiles, grid, lds, j, st)
+  }
   if (s.rule_bytes == 8) {
     SNP_FLAGS_DISPATCH(launch_pull_batch_rf, 8, s, members, tiles, ntiles, grid, lds, j, st)
   }

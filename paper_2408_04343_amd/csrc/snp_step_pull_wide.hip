@@ -66,7 +66,8 @@ static hipError_t launch_wide_w(const SysDev& s, int32_t j, hipStream_t st) {
   recv_wide_kernel<W><<<(s.q + per - 1) / per, WIDE_NT, 0, st>>>(s, j);
   if (s.n_heavy > 0) {
     const dim3 g((s.n_heavy + per - 1) / per);
-    if (s.rule_bytes == 8) sel_wide_kernel<8><<<g, WIDE_NT, 0, st>>>(s, j);
+    if (s.rule_bytes == 4) sel_wide_kernel<4><<<g, WIDE_NT, 0, st>>>(s, j);
+    else if (s.rule_bytes == 8) sel_wide_kernel<8><<<g, WIDE_NT, 0, st>>>(s, j);
     else sel_wide_kernel<16><<<g, WIDE_NT, 0, st>>>(s, j);
   }
   hipError_t e = hipGetLastError();

@@ -270,6 +270,7 @@ static hipError_t launch_push_batch_r(const SysDev& s, const SysDev* members, co
 }
 
 hipError_t launch_step_push(const SysDev& s, int32_t j, hipStream_t st) {
+  if (s.rule_bytes == 4) return launch_push_r<4>(s, j, st);
   return s.rule_bytes == 8 ? launch_push_r<8>(s, j, st) : launch_push_r<16>(s, j, st);
 }
 
@@ -304,11 +305,13 @@ static hipError_t launch_push_wide_r(const SysDev& s, int32_t j, hipStream_t st)
 
 hipError_t launch_step_push_wide(const SysDev& s, int32_t j, hipStream_t st) {
   if (!s.elist || !s.ecnt || (s.n_heavy > 0 && !s.hsel)) return hipErrorInvalidValue;
+  if (s.rule_bytes == 4) return launch_push_wide_r<4>(s, j, st);
   return s.rule_bytes == 8 ? launch_push_wide_r<8>(s, j, st) : launch_push_wide_r<16>(s, j, st);
 }
 
 hipError_t launch_step_push_batch(const SysDev& s, const SysDev* members, const int2* tiles,
                                   const int32_t* ntiles, int32_t grid, int32_t j, hipStream_t st) {
+  if (s.rule_bytes == 4) return launch_push_batch_r<4>(s, members, tiles, ntiles, grid, j, st);
   return s.rule_bytes == 8 ? launch_push_batch_r<8>(s, members, tiles, ntiles, grid, j, st)
                            : launch_push_batch_r<16>(s, members, tiles, ntiles, grid, j, st);
 }

@@ -220,7 +220,8 @@ extern "C" int snp_expand(snp_sys* s, int32_t nstates, const int32_t* C, const i
   a.P = dP;
   const int nt = 64;
   const unsigned g1 = (unsigned)((nstates + nt - 1) / nt);
-  if (s->d.rule_bytes == 8) tree_count_kernel<8><<<g1, nt, 0, st>>>(a, counts);
+  if (s->d.rule_bytes == 4) tree_count_kernel<4><<<g1, nt, 0, st>>>(a, counts);
+  else if (s->d.rule_bytes == 8) tree_count_kernel<8><<<g1, nt, 0, st>>>(a, counts);
   else tree_count_kernel<16><<<g1, nt, 0, st>>>(a, counts);
   TCHK(hipGetLastError());
   std::vector<int64_t> off((size_t)nstates + 1, 0);
@@ -248,7 +249,8 @@ extern "C" int snp_expand(snp_sys* s, int32_t nstates, const int32_t* C, const i
   TCHK(hipMemcpyAsync(doff, off.data(), 8 * ((size_t)nstates + 1), hipMemcpyHostToDevice, st));
   TCHK(hipMemsetAsync(ovf, 0, 4, st));
   const unsigned g2 = (unsigned)((total + nt - 1) / nt);
-  if (s->d.rule_bytes == 8) tree_expand_kernel<8><<<g2, nt, 0, st>>>(a, doff, total, oC, oD, oP, par, em, ovf);
+  if (s->d.rule_bytes == 4) tree_expand_kernel<4><<<g2, nt, 0, st>>>(a, doff, total, oC, oD, oP, par, em, ovf);
+  else if (s->d.rule_bytes == 8) tree_expand_kernel<8><<<g2, nt, 0, st>>>(a, doff, total, oC, oD, oP, par, em, ovf);
   else tree_expand_kernel<16><<<g2, nt, 0, st>>>(a, doff, total, oC, oD, oP, par, em, ovf);
   TCHK(hipGetLastError());
   int32_t overflow = 0;

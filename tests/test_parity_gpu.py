@@ -83,6 +83,34 @@ def test_config1_every_step(binding, layout, sem_name, sem):
     compare_every_step(binding, spec, layout, sem_name, sem, 100)
 
 
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "ell", "sparse",
+                                    "optimized_atomic", "csr_push_wide"])
+@pytest.mark.parametrize("rule_bytes", [4, 8, 16])
+def test_rule_record_widths_every_step(binding, layout, rule_bytes):
+    # the 4-, 8- and 16-byte rule records give the same trajectory; 4 is
+    # chosen by default when every field fits, as it does here
+    spec = wl.small_random(41, 5000, max_deg=9, max_rules=4, dmax=3, c0max=8, select=wl.SELECT_HASH)
+    g = gpu_of(binding, spec, layout, "standard", rule_bytes=rule_bytes)
+    assert g.info()["rule_bytes"] == rule_bytes
+    g.close()
+    for sem_name, sem in SEMS:
+        compare_every_step(binding, spec, layout, sem_name, sem, 30, rule_bytes=rule_bytes)
+
+
+def test_rule_records_fall_back_to_wider(binding):
+    # a field beyond the 4-byte format (c = 300, d = 20, p = 40) takes 8 bytes,
+    # beyond the 8-byte one (p = 300) 16 bytes
+    base = [(0, 1, 1, 1, 1, 0), (1, 1, 0, 1, 1, 0)]
+    for extra, width in (((0, 300, 0, 300, 1, 0), 8), ((0, 2, 0, 2, 1, 20), 8), ((0, 2, 0, 2, 40, 0), 8),
+                         ((0, 2, 0, 2, 300, 0), 16), ((0, 1500, 0, 1500, 1, 0), 8)):
+        g = binding.System(2, [3, 0], base + [extra], [0], [1])
+        assert g.info()["rule_bytes"] == width, extra
+        g.step(5)
+        o = orc.OracleSystem(2, [3, 0], base + [extra], [0], [1])
+        o.step(5)
+        assert g.read_config().tolist() == o.read()["C"].tolist()
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("q", [1, 7, 2047, 2048, 2049, 6001])
 def test_hash_ragged_sizes_every_step(binding, layout, q):
