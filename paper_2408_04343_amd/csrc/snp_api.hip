@@ -572,6 +572,11 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
     d.emit_w = o.emit_bits;
   }
   d.sel_wave = maxr > SEL_LIGHT_RULES ? 1 : 0;
+  d.div_periods = 0;
+  for (int32_t x = 0; x < m; ++x) {
+    const uint32_t per = (uint32_t)rec[x].period;
+    if (per & (per - 1u)) d.div_periods = 1;
+  }
   d.pull_wide = pull_wide(o.pull_mode, q, nsyn) ? 1 : 0;
   d.pull_gather = !d.pull_wide && pull_gathers(o.pull_mode, q, nsyn, d.emit_w) ? 1 : 0;
   d.pull_tb = (d.pull_gather || d.pull_wide) ? PULL_TB_GATHER : PULL_TB_STAGED;

@@ -98,6 +98,12 @@ __device__ __forceinline__ bool rule_applies(const Rule& r, int32_t n) {
   return ge & (d % per == 0u);
 }
 
+// The same test for a system whose periods are all 0 or powers of two.
+__device__ __forceinline__ bool rule_applies_pow2(const Rule& r, int32_t n) {
+  const uint32_t d = (uint32_t)(n - r.lo), per = (uint32_t)r.period;
+  return (n >= r.lo) & ((d & (per - 1u)) == 0u);
+}
+
 // What a neuron needs to take its step, loaded ahead of its use.  The rule
 // records are named fields (not an array) so that they stay in registers.
 template <int RB>
@@ -126,9 +132,21 @@ __device__ __forceinline__ int32_t choose_rule(const SysDev& s, int32_t i, int64
   constexpr int PF = kPrefetch<RB>;
   const int32_t n = in.C, r0 = in.r0, r1 = in.r1;
   // the prefetched records are tested without branches (a record past r1
-  // is a valid stand-in whose result is masked off)
-#define SNP_APPLIES(X) ((X < PF) & (r0 + X < r1) & rule_applies(decode(pf_at<X, RB>(in)), n))
-  const bool a0 = SNP_APPLIES(0), a1 = SNP_APPLIES(1), a2 = SNP_APPLIES(2), a3 = SNP_APPLIES(3);
+  // is a valid stand-in whose result is masked off); without periods that
+  // need a division (a uniform test) there is no branch per record either
+  bool a0, a1, a2, a3;
+#define SNP_APPLIES(X, F) ((X < PF) & (r0 + X < r1) & F(decode(pf_at<X, RB>(in)), n))
+  if (!s.div_periods) {
+    a0 = SNP_APPLIES(0, rule_applies_pow2);
+    a1 = SNP_APPLIES(1, rule_applies_pow2);
+    a2 = SNP_APPLIES(2, rule_applies_pow2);
+    a3 = SNP_APPLIES(3, rule_applies_pow2);
+  } else {
+    a0 = SNP_APPLIES(0, rule_applies);
+    a1 = SNP_APPLIES(1, rule_applies);
+    a2 = SNP_APPLIES(2, rule_applies);
+    a3 = SNP_APPLIES(3, rule_applies);
+  }
 #undef SNP_APPLIES
   if (s.sel == SEL_FIRST) {
     const uint32_t hit = (uint32_t)a0 | ((uint32_t)a1 << 1) | ((uint32_t)a2 << 2) | ((uint32_t)a3 << 3);

@@ -77,6 +77,7 @@ struct SysDev {
   const int32_t* rs;         // [q+1] rules of neuron i: slots rs[i] .. rs[i+1]-1
   int32_t rule_bytes;        // 4: rules4 holds the rule vector, 8: rules8, 16: rules
   int32_t sel_wave;          // 1: some neuron has more rules than a thread scans alone
+  int32_t div_periods;       // 1: some rule's period is neither 0 nor a power of two
   const RuleRec* rules;      // [m] in slot order
   const uint2* rules8;       // [m] in slot order, packed
   const uint32_t* rules4;    // [m] in slot order, packed into 4 bytes

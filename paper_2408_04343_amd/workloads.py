@@ -258,13 +258,13 @@ def sort_system(values) -> SnpSpec:
 
 
 def small_random(seed: int, q: int, max_deg: int = 4, max_rules: int = 3, dmax: int = 2,
-                 c0max: int = 6, select=SELECT_FIRST, steps: int = 50, kmax=3, pmax=2) -> SnpSpec:
+                 c0max: int = 6, select=SELECT_FIRST, steps: int = 50, kmax=3, pmax=2, mmax=2) -> SnpSpec:
     """A small random system for parity sweeps (ragged sizes, mixed rule forms)."""
     rng = np.random.default_rng([seed, 99])
     deg = rng.integers(0, min(max_deg, q - 1) + 1, size=q)
     nr = rng.integers(0, max_rules + 1, size=q)
     src, dst = distinct_targets(rng, q, deg)
-    rules = random_rules(rng, nr, dmax, kmax=kmax, pmax=pmax)
+    rules = random_rules(rng, nr, dmax, kmax=kmax, mmax=mmax, pmax=pmax)
     spikes0 = rng.integers(0, c0max + 1, size=q).astype(np.int32)
     return SnpSpec("small%d" % seed, q, spikes0, rules, src, dst, select,
                    system_seed(seed, 7), steps)

@@ -221,7 +221,7 @@ def test_sort_worst_case_input_n100():
 
 def _tiny_systems():
     """All systems with q = 2 on a fixed grid of parameters plus q = 3 samples."""
-    exprs = [(1, 0), (2, 0), (1, 1), (0, 1), (2, 2)]     # a, a^2, a+, a*, a^2(a^2)*
+    exprs = [(1, 0), (2, 0), (1, 1), (0, 1), (2, 2), (1, 3)]     # a, a^2, a+, a*, a^2(a^2)*, a(a^3)*
     for e0, e1 in itertools.product(exprs, repeat=2):
         for d0, d1 in ((0, 0), (1, 0), (2, 1)):
             for c0 in ((2, 1), (3, 0), (1, 3)):

@@ -97,6 +97,18 @@ def test_rule_record_widths_every_step(binding, layout, rule_bytes):
         compare_every_step(binding, spec, layout, sem_name, sem, 30, rule_bytes=rule_bytes)
 
 
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "optimized", "ell_atomic", "sparse_wide"])
+@pytest.mark.parametrize("rule_bytes", [4, 8, 16])
+def test_periods_that_divide_every_step(binding, layout, rule_bytes):
+    # periods 1..7 (3, 5, 6, 7 need a division) and larger counts
+    spec = wl.small_random(43, 3000, max_deg=6, max_rules=4, dmax=2, c0max=24, kmax=5, mmax=7,
+                           select=wl.SELECT_HASH)
+    assert set(spec.rules[:, 2].tolist()) >= {3, 5, 7}
+    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 30, rule_bytes=rule_bytes)
+    spec = wl.small_random(44, 3000, max_deg=6, max_rules=4, dmax=2, c0max=24, kmax=5, mmax=7)
+    compare_every_step(binding, spec, layout, "paper_kernel", orc.SEM_PAPER_KERNEL, 30, rule_bytes=rule_bytes)
+
+
 def test_rule_records_fall_back_to_wider(binding):
     # a field beyond the 4-byte format (c = 300, d = 20, p = 40) takes 8 bytes,
     # beyond the 8-byte one (p = 300) 16 bytes
