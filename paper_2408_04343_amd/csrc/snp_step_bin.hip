@@ -237,12 +237,12 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   constexpr bool DIG = (FLAGS & F_DIGEST) != 0;
   constexpr bool CNT = (FLAGS & F_COUNTERS) != 0;
   const BinLds L = bin_lds(lds, s.bnb);
-  int64_t k;
-  if (!step_prologue(s, tile, j, k)) return;
   const int32_t nb = s.bnb;
   const int32_t t0 = tile * BIN_TILE;
   const int tid = threadIdx.x;
 
+  // the tile's state is loaded before the step index (its addresses do not
+  // depend on it), so that the two load latencies overlap
   NeuronIn<RB> in[BIN_NPT];
 #pragma unroll
   for (int r = 0; r < BIN_NPT; ++r) {
@@ -254,8 +254,11 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     } else {
       in[r].meta = 0;
     }
-    L.acc[tid + r * BIN_NT] = 0;
   }
+  int64_t k;
+  if (!step_prologue(s, tile, j, k)) return;
+#pragma unroll
+  for (int r = 0; r < BIN_NPT; ++r) L.acc[tid + r * BIN_NT] = 0;
   for (int32_t b = tid; b < nb; b += BIN_NT) {
     L.offp[b] = s.boffp[(size_t)tile * nb + b];
     L.lcnt[b] = 0;

@@ -41,11 +41,11 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
   uint32_t* stage = lds + PULL_TILE;         // [TILE_WORDS] emitted values of this tile
   uint16_t* defer = (uint16_t*)(stage + TILE_WORDS);  // [PULL_TILE] neurons whose rules a wave scans
   uint32_t* chunk = stage + TILE_WORDS + PULL_TILE / 2;  // emitted values of one source chunk (16-byte aligned)
-  int64_t k;
-  if (!step_prologue(s, tile, j, k)) return;
   const int32_t t0 = tile * PULL_TILE;
   const int tid = threadIdx.x;
 
+  // the tile's state is loaded before the step index (its addresses do not
+  // depend on it), so that the two load latencies overlap
   NeuronIn<RB> in[PULL_NPT];
 #pragma unroll
   for (int r = 0; r < PULL_NPT; ++r) {
@@ -57,8 +57,11 @@ __device__ __forceinline__ void pull_body(const SysDev& s, int32_t tile, int32_t
     } else {
       in[r].meta = 0;
     }
-    acc[tid + r * PULL_NT] = 0;
   }
+  int64_t k;
+  if (!step_prologue(s, tile, j, k)) return;
+#pragma unroll
+  for (int r = 0; r < PULL_NPT; ++r) acc[tid + r * PULL_NT] = 0;
   for (int w = tid; w < TILE_WORDS; w += PULL_NT) stage[w] = 0u;
   if (tid == 0) *ndefer = 0;
 
