@@ -325,7 +325,7 @@ typedef struct snp_info_t {
   int64_t nsyn;          /* synapses                                         */
   int32_t zmax;          /* MaxOutDegree                                     */
   int32_t layout;        /* SNP_LAYOUT_* in use                              */
-  int32_t rule_bytes;    /* bytes per rule record on the device (8 or 16)    */
+  int32_t rule_bytes;    /* bytes per rule record on the device (4, 8, 16)  */
   int32_t emit_bits;     /* CSR_PULL: bits per emitted value                 */
   int32_t pull_tile_log2;/* CSR_PULL: log2 of the neurons per block          */
   int32_t pull_chunk;    /* CSR_PULL: sources per LDS chunk                  */
@@ -374,7 +374,8 @@ int snp_set_step_limit(snp_sys* sys, int64_t limit);
  * key, halting flag and step limit, so a member's computation is the same
  * as when it runs alone.  Members must share layout, rule record size,
  * emit width and SNP_F_DIGEST / SNP_F_COUNTERS flags (SNP_ENOTSUP
- * otherwise); members of both reception modes (SNP_PULL_* / SNP_PUSH_*) may
+ * otherwise; SNP_F_RULES8 or SNP_F_WIDE_RULES at creation give systems whose
+ * rule values differ in range one record size); members of both reception modes (SNP_PULL_* / SNP_PUSH_*) may
  * mix, at one launch per mode and step.  While in a batch a handle refuses snp_step,
  * snp_write_state and snp_destroy (SNP_EBUSY); its read calls work.      */
 typedef struct snp_batch snp_batch;
