@@ -299,9 +299,10 @@ int snp_set_synapses(snp_sys* sys, int64_t nsyn, const int32_t* syn_src, const i
  * *nchildren = the number of successors.  With any output NULL only
  * *nchildren is set (a size query); cap < *nchildren is SNP_EINVAL.  More
  * than 2^31 successors: SNP_ENOTSUP; a successor count beyond int32:
- * SNP_EOVERFLOW.  Synchronous (returns when the outputs are written); meant
- * for small systems (each successor costs O(q + rules + synapses) on one
- * GPU thread). */
+ * SNP_EOVERFLOW; a handle in a batch: SNP_EBUSY.  Synchronous (returns when
+ * the outputs are written) on the handle's stream; allocates and frees its
+ * own device buffers.  Meant for small systems (each successor costs
+ * O(q + rules + synapses) on one GPU thread). */
 int snp_expand(snp_sys* sys, int32_t nstates, const int32_t* C, const int32_t* D, const int32_t* pend,
                int64_t cap, int32_t* child_C, int32_t* child_D, int32_t* child_pend, int32_t* child_parent,
                int64_t* nchildren);

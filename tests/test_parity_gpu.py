@@ -832,6 +832,27 @@ def test_tree_levels_equal_oracle(binding, layout):
                     for x in range(len(lv["C"]))}
 
 
+def test_expand_on_clones_and_batched_handles(binding):
+    spec = wl.small_random(78, 6, max_deg=3, max_rules=3, dmax=2, c0max=5)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    g = binding.System.from_spec(spec)
+    c = g.clone()                       # shares the rules and synapses
+    root = (spec.spikes0, np.zeros(spec.q, np.int32), np.full(spec.q, -1, np.int32))
+    want = o.children(*root)
+    for h in (g, c):
+        got = h.expand(*root)
+        assert len(got["parent"]) == len(want)
+        for x, (cc, d, p) in enumerate(want):
+            assert got["C"][x].tolist() == cc.tolist() and got["D"][x].tolist() == d.tolist()
+            assert got["pend"][x].tolist() == p.tolist()
+    b = binding.Batch([c])
+    with pytest.raises(binding.SnpError) as ei:
+        c.expand(*root)
+    assert ei.value.status == -5
+    b.close()
+    assert len(c.expand(*root)["parent"]) == len(want)
+
+
 def test_expand_hand_examples_and_limits(binding):
     rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
     g = binding.System(1, [4], rules, [], [])
