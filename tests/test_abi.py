@@ -129,3 +129,24 @@ def test_binding_structs_match_header_layout(tmp_path):
         assert got[(cname, "sizeof")] == ct.sizeof(py), cname
         for f, _t in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_binding_constants_match_header():
+    # every layout, choice, delay reading, reception mode and flag the header
+    # defines has the same value in the binding
+    from paper_2408_04343_amd import binding
+    text = open(os.path.join(ROOT, "include", "snp.h")).read()
+    defs = {m.group(1): int(m.group(2), 0)
+            for m in re.finditer(r"^#define SNP_(\w+)\s+\(?(-?(?:0x)?[0-9a-fA-F]+)u?\)?", text, flags=re.M)}
+    prefixes = ("LAYOUT_", "SELECT_", "SEM_", "PULL_", "PUSH_", "F_")
+    checked = 0
+    for name, value in defs.items():
+        if not name.startswith(prefixes):
+            continue
+        assert getattr(binding, name) == value, name
+        checked += 1
+    assert checked >= 26
+    # the string names the binding accepts map onto the same values
+    assert binding.LAYOUTS["sparse"] == defs["LAYOUT_SPARSE"]
+    assert binding.PUSH_MODES["wide"] == defs["PUSH_WIDE"]
+    assert binding.PULL_MODES["wide"] == defs["PULL_WIDE"]
