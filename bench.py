@@ -190,7 +190,7 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
                               "smallest, median and largest member, each alone", "members": tuned}}
 
 
-def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64):
+def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64, pull_mode="gather"):
     """Config 5: Poisson arrivals of requests with q ~ logU[1,000, 1,048,576]
     and steps ~ logU[100, 10,000], hash choice.  Each request clones the
     template nearest to its size (log scale), so a pool of templates stands in
@@ -201,8 +201,11 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     t0 = time.time()
     tq = np.unique(np.round(np.exp(np.linspace(np.log(1000), np.log(1 << 20), n_templates))).astype(int))
     stream = torch.cuda.Stream()
+    # every request runs batched, where reading emitted values from device
+    # memory (gather) is the fastest pull schedule measured (config 4)
     templates = [binding.System.from_spec(wl.config5_system(1000 + j, int(q), 0, 0), emit_bits=2,
-                                          stream=stream.cuda_stream) for j, q in enumerate(tq)]
+                                          pull_mode=pull_mode, stream=stream.cuda_stream)
+                 for j, q in enumerate(tq)]
     prep_s = time.time() - t0
     logq = np.log(tq)
 
@@ -229,7 +232,7 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     out = {"workload": "config5-served: Poisson arrivals, q ~ logU[1,000, 1,048,576] (nearest of %d "
                        "templates), steps ~ logU[100, 10,000], Poisson(16) out-degree, hash choice"
                        % len(tq),
-           "templates": len(tq), "template_prep_s": round(prep_s, 1), "tick_steps": tick,
+           "templates": len(tq), "template_pull_mode": pull_mode, "template_prep_s": round(prep_s, 1), "tick_steps": tick,
            "at_rate": over}
     if capacity_nu:
         sub_rate = 0.7 * capacity_nu / mean_work
