@@ -632,6 +632,30 @@ def test_batch_rejects_wide_members(binding):
     c.step(3)
 
 
+def test_batch_members_share_a_rule_record_width(binding):
+    small = wl.small_random(3, 200, max_rules=3)                 # fits the 4-byte records
+    big_rules = small.rules.copy()
+    big_rules[0, 1] = big_rules[0, 3] = 300                     # c = 300 needs 8 bytes
+    a = binding.System.from_spec(small, layout="csr_pull")
+    c = binding.System(small.q, small.spikes0, big_rules, small.src, small.dst, layout="csr_pull")
+    assert (a.info()["rule_bytes"], c.info()["rule_bytes"]) == (4, 8)
+    b = binding.Batch([a])
+    with pytest.raises(binding.SnpError) as ei:
+        b.add(c)
+    assert ei.value.status == -6
+    b.close()
+    # forcing 8-byte records makes them one batch, with the same steps as alone
+    a8 = binding.System.from_spec(small, layout="csr_pull", rule_bytes=8)
+    c2 = binding.System(small.q, small.spikes0, big_rules, small.src, small.dst, layout="csr_pull")
+    ref = binding.System.from_spec(small, layout="csr_pull")
+    b = binding.Batch([a8, c2])
+    b.step(20)
+    b.sync()
+    b.close()
+    ref.step(20)
+    assert np.array_equal(a8.read_config(), ref.read_config())
+
+
 def test_batch_rejects_mixed_members(binding):
     a = binding.System.from_spec(wl.small_random(1, 100), layout="csr_pull", emit_bits=2)
     c = binding.System.from_spec(wl.small_random(2, 100), layout="csr_push")
