@@ -222,19 +222,23 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
                int64_t nsyn, const int32_t* syn_src, const int32_t* syn_dst,
                const snp_opts* opts, snp_sys** out);
 
-/* Enqueues k more transition steps on the handle's stream and returns
- * without waiting.  Steps after the system halts do nothing (halting is
- * absorbing).  k <= 0 does nothing.                                        */
+/* k iterations of the main loop of Alg. 1 (Sec. 2): SV_CALC (Alg. 2), the
+ * choice that replaces SAMPLE_ONE (Sec. 5.2), STEP (Sec. 5.3, Alg. 3-5) and
+ * UPDATE_DELAYS, each iteration one transition C_k -> C_{k+1}.  Enqueues them
+ * on the handle's stream and returns without waiting.  Steps after the
+ * system halts do nothing (halting is absorbing).  k <= 0 does nothing.    */
 int snp_step(snp_sys* sys, int64_t k);
 
-/* Waits for the stream, then reports the number of executed steps and
- * whether the current configuration is halted (no rule applicable in any
- * open neuron and every neuron open).  Either pointer may be NULL.
- * Returns SNP_EOVERFLOW if a count ever left the int32 range.              */
+/* The step counter k of Alg. 1 and its stop test (Sec. 2, Alg. 1; the loop
+ * ends when no rule is applicable, read here with the delays: no rule
+ * applicable in any open neuron and every neuron open).  Waits for the
+ * stream, then reports the number of executed steps and whether the current
+ * configuration is halted.  Either pointer may be NULL.  Returns
+ * SNP_EOVERFLOW if a count ever left the int32 range.                     */
 int snp_steps_done(snp_sys* sys, int64_t* steps, int32_t* halted);
 
-/* Wait for the stream, then copy the current configuration vector C_k
- * (host [q]).                                                              */
+/* The configuration vector C_k of Sec. 2 (spikes held by each neuron after
+ * k executed steps).  Waits for the stream, then copies it (host [q]).     */
 int snp_read_config(snp_sys* sys, int32_t* out);
 
 /* Spiking vector of the last executed step in neuron form (Sec. 4,
@@ -242,7 +246,8 @@ int snp_read_config(snp_sys* sys, int32_t* out);
  * none (host [q]).  All -1 before the first step.                          */
 int snp_read_spiking(snp_sys* sys, int32_t* out);
 
-/* Delays vector D_k: 0 = open, > 0 = steps until the neuron opens (host [q]). */
+/* The delays vector D_k of Sec. 2 (UPDATE_DELAYS in Alg. 1): 0 = open, > 0 =
+ * steps until the neuron opens (host [q]).                                 */
 int snp_read_delays(snp_sys* sys, int32_t* out);
 
 /* Rule whose spikes are still to be sent (STANDARD mode, D > 0), -1 if none

@@ -64,51 +64,55 @@ def _load():
     global _lib
     if _lib is None:
         build()
-        lib = ct.CDLL(_LIB)
-        P = ct.POINTER
-        lib.orc_create.argtypes = [ct.c_int32, P(ct.c_int32), ct.c_int32, P(Rule), ct.c_int64,
-                                   P(ct.c_int32), P(ct.c_int32), ct.c_int, ct.c_int, ct.c_uint64,
-                                   P(ct.c_void_p)]
-        lib.orc_create.restype = ct.c_int
-        lib.orc_destroy.argtypes = [ct.c_void_p]
-        lib.orc_step.argtypes = [ct.c_void_p, ct.c_int64]
-        lib.orc_step.restype = ct.c_int64
-        lib.orc_step_record.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32),
-                                        P(ct.c_int32), P(ct.c_uint64), P(Counters)]
-        lib.orc_step_record.restype = ct.c_int64
-        lib.orc_steps_done.argtypes = [ct.c_void_p]
-        lib.orc_steps_done.restype = ct.c_int64
-        lib.orc_halted.argtypes = [ct.c_void_p]
-        lib.orc_halted.restype = ct.c_int
-        lib.orc_overflow.argtypes = [ct.c_void_p]
-        lib.orc_overflow.restype = ct.c_int
-        lib.orc_read.argtypes = [ct.c_void_p, P(ct.c_int32), P(ct.c_int32), P(ct.c_int32), P(ct.c_int32)]
-        lib.orc_read_c64.argtypes = [ct.c_void_p, P(ct.c_int64)]
-        lib.orc_digest.argtypes = [ct.c_void_p]
-        lib.orc_digest.restype = ct.c_uint64
-        lib.orc_counters_get.argtypes = [ct.c_void_p, P(Counters)]
-        lib.orc_mix64.argtypes = [ct.c_uint64]
-        lib.orc_mix64.restype = ct.c_uint64
-        lib.orc_hash.argtypes = [ct.c_uint64, ct.c_int64, ct.c_int32]
-        lib.orc_hash.restype = ct.c_uint64
-        lib.orc_pick.argtypes = [ct.c_uint64, ct.c_uint32]
-        lib.orc_pick.restype = ct.c_uint32
-        lib.orc_paper_sizes.argtypes = [ct.c_int64, ct.c_int64, ct.c_int64, P(ct.c_int64), P(ct.c_int64),
-                                        P(ct.c_int64)]
-        lib.orc_max_outdeg.argtypes = [ct.c_void_p]
-        lib.orc_max_outdeg.restype = ct.c_int32
-        lib.orc_build_ell.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32), P(ct.c_int32)]
-        lib.orc_build_sy.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
-        lib.orc_set_synapses.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32)]
-        lib.orc_set_synapses.restype = ct.c_int
-        lib.orc_set_state.argtypes = [ct.c_void_p, P(ct.c_int32), P(ct.c_int32), P(ct.c_int32)]
-        lib.orc_set_state.restype = ct.c_int
-        lib.orc_applicable.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
-        lib.orc_applicable.restype = ct.c_int32
-        lib.orc_step_choice.argtypes = [ct.c_void_p, P(ct.c_int32)]
-        lib.orc_step_choice.restype = ct.c_int
-        _lib = lib
+        _lib = bind(ct.CDLL(_LIB))
     return _lib
+
+
+def bind(lib):
+    """Declares the argument and result types of a loaded oracle library."""
+    P = ct.POINTER
+    lib.orc_create.argtypes = [ct.c_int32, P(ct.c_int32), ct.c_int32, P(Rule), ct.c_int64,
+                               P(ct.c_int32), P(ct.c_int32), ct.c_int, ct.c_int, ct.c_uint64,
+                               P(ct.c_void_p)]
+    lib.orc_create.restype = ct.c_int
+    lib.orc_destroy.argtypes = [ct.c_void_p]
+    lib.orc_step.argtypes = [ct.c_void_p, ct.c_int64]
+    lib.orc_step.restype = ct.c_int64
+    lib.orc_step_record.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32),
+                                    P(ct.c_int32), P(ct.c_uint64), P(Counters)]
+    lib.orc_step_record.restype = ct.c_int64
+    lib.orc_steps_done.argtypes = [ct.c_void_p]
+    lib.orc_steps_done.restype = ct.c_int64
+    lib.orc_halted.argtypes = [ct.c_void_p]
+    lib.orc_halted.restype = ct.c_int
+    lib.orc_overflow.argtypes = [ct.c_void_p]
+    lib.orc_overflow.restype = ct.c_int
+    lib.orc_read.argtypes = [ct.c_void_p, P(ct.c_int32), P(ct.c_int32), P(ct.c_int32), P(ct.c_int32)]
+    lib.orc_read_c64.argtypes = [ct.c_void_p, P(ct.c_int64)]
+    lib.orc_digest.argtypes = [ct.c_void_p]
+    lib.orc_digest.restype = ct.c_uint64
+    lib.orc_counters_get.argtypes = [ct.c_void_p, P(Counters)]
+    lib.orc_mix64.argtypes = [ct.c_uint64]
+    lib.orc_mix64.restype = ct.c_uint64
+    lib.orc_hash.argtypes = [ct.c_uint64, ct.c_int64, ct.c_int32]
+    lib.orc_hash.restype = ct.c_uint64
+    lib.orc_pick.argtypes = [ct.c_uint64, ct.c_uint32]
+    lib.orc_pick.restype = ct.c_uint32
+    lib.orc_paper_sizes.argtypes = [ct.c_int64, ct.c_int64, ct.c_int64, P(ct.c_int64), P(ct.c_int64),
+                                    P(ct.c_int64)]
+    lib.orc_max_outdeg.argtypes = [ct.c_void_p]
+    lib.orc_max_outdeg.restype = ct.c_int32
+    lib.orc_build_ell.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32), P(ct.c_int32)]
+    lib.orc_build_sy.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
+    lib.orc_set_synapses.argtypes = [ct.c_void_p, ct.c_int64, P(ct.c_int32), P(ct.c_int32)]
+    lib.orc_set_synapses.restype = ct.c_int
+    lib.orc_set_state.argtypes = [ct.c_void_p, P(ct.c_int32), P(ct.c_int32), P(ct.c_int32)]
+    lib.orc_set_state.restype = ct.c_int
+    lib.orc_applicable.argtypes = [ct.c_void_p, ct.c_int32, P(ct.c_int32)]
+    lib.orc_applicable.restype = ct.c_int32
+    lib.orc_step_choice.argtypes = [ct.c_void_p, P(ct.c_int32)]
+    lib.orc_step_choice.restype = ct.c_int
+    return lib
 
 
 def _ip(a):

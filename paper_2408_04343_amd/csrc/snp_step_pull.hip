@@ -12,8 +12,9 @@ size_t pull_lds_bytes(const SysDev& s) {
   return (size_t)(tile * 4 + tile * s.emit_w / 32 * 4 + tile * 2 + cwords * 4);
 }
 
-// Lets the staged pull kernels use up to `bytes` of dynamic LDS (the gather
-// kernels stay below the default limit).
+// Lets the staged pull kernels (every emit width, rule record size and
+// flag set) use up to `bytes` of dynamic LDS; the gather kernels stay below
+// the default limit.
 hipError_t prepare_pull_kernels(size_t bytes) {
   hipError_t e = hipSuccess;
 #define SNP_SET_LDS(WW, RR, FL)                                                                   \
@@ -26,7 +27,7 @@ hipError_t prepare_pull_kernels(size_t bytes) {
 #define SNP_SET_LDS_R(WW, RR) \
   SNP_SET_LDS(WW, RR, 0u) SNP_SET_LDS(WW, RR, F_DIGEST) SNP_SET_LDS(WW, RR, F_COUNTERS) \
   SNP_SET_LDS(WW, RR, F_DIGEST | F_COUNTERS)
-#define SNP_SET_LDS_W(WW) SNP_SET_LDS_R(WW, 8) SNP_SET_LDS_R(WW, 16)
+#define SNP_SET_LDS_W(WW) SNP_SET_LDS_R(WW, 4) SNP_SET_LDS_R(WW, 8) SNP_SET_LDS_R(WW, 16)
   SNP_SET_LDS_W(1) SNP_SET_LDS_W(2) SNP_SET_LDS_W(4) SNP_SET_LDS_W(8) SNP_SET_LDS_W(16)
 #undef SNP_SET_LDS_W
 #undef SNP_SET_LDS_R

@@ -106,6 +106,37 @@ def random_rules(rng: np.random.Generator, nrules: np.ndarray, dmax: int, kmax=3
     return np.stack([neuron, k, period, k, p, d], axis=1).astype(np.int32)
 
 
+def general_rules(rng: np.random.Generator, nrules: np.ndarray, dmax: int, kmax=4, pmax=3,
+                  long_delays: int = 0):
+    """Rules of every form the definition allows, for parity sweeps.  Per rule
+    the expression is, with equal probability, a^k, a^k (a^j)*, a* (base 0,
+    period 1), a+ (base 1, period 1) or a^0 (base 0, period 0, which no count
+    >= c matches); k ~ U{1..kmax}, j ~ U{1..3}.  c is unrelated to the
+    expression: with equal probability the expression's base (at least 1),
+    below it, or up to 3 above it.  p ~ U{0..pmax} (0 = forgetting), d ~
+    U{0..dmax}; `long_delays` rules (if any) get d ~ U{16..40}, beyond the
+    4-bit delay field of the smallest rule record.  Listed neuron by neuron."""
+    nrules = np.asarray(nrules, dtype=np.int64)
+    m = int(nrules.sum())
+    neuron = np.repeat(np.arange(nrules.size, dtype=np.int64), nrules)
+    form = rng.integers(0, 5, size=m)
+    k = rng.integers(1, kmax + 1, size=m)
+    j = rng.integers(1, 4, size=m)
+    base = np.select([form == 0, form == 1, form == 2, form == 3], [k, k, 0, 1], 0)
+    period = np.select([form == 1, form == 2, form == 3], [j, 1, 1], 0)
+    how = rng.integers(0, 3, size=m)
+    b1 = np.maximum(base, 1)
+    below = 1 + (rng.random(m) * np.maximum(b1 - 1, 1)).astype(np.int64)
+    above = b1 + rng.integers(1, 4, size=m)
+    c = np.where(how == 0, b1, np.where(how == 1, np.minimum(below, b1), above))
+    p = rng.integers(0, pmax + 1, size=m)
+    d = rng.integers(0, dmax + 1, size=m)
+    if long_delays and m:
+        at = rng.choice(m, size=min(long_delays, m), replace=False)
+        d[at] = rng.integers(16, 41, size=at.size)
+    return np.stack([neuron, base, period, c, p, d], axis=1).astype(np.int32)
+
+
 def truncated_power_law(rng: np.random.Generator, n: int, alpha: float, kmin: int, kmax: int):
     """Discrete P(k) proportional to k^-alpha on [kmin, kmax], by inverse CDF."""
     ks = np.arange(kmin, kmax + 1, dtype=np.float64)
@@ -258,13 +289,22 @@ def sort_system(values) -> SnpSpec:
 
 
 def small_random(seed: int, q: int, max_deg: int = 4, max_rules: int = 3, dmax: int = 2,
-                 c0max: int = 6, select=SELECT_FIRST, steps: int = 50, kmax=3, pmax=2, mmax=2) -> SnpSpec:
-    """A small random system for parity sweeps (ragged sizes, mixed rule forms)."""
+                 c0max: int = 6, select=SELECT_FIRST, steps: int = 50, kmax=3, pmax=2, mmax=2,
+                 general: bool = False, long_delays: int = 0) -> SnpSpec:
+    """A small random system for parity sweeps (ragged sizes, mixed rule forms).
+    general=True draws the rules with `general_rules` (every expression form,
+    c unrelated to the expression, forgetting rules, `long_delays` delays
+    above 15) and lists them in a shuffled order, so that rule ids are not
+    grouped by neuron."""
     rng = np.random.default_rng([seed, 99])
     deg = rng.integers(0, min(max_deg, q - 1) + 1, size=q)
     nr = rng.integers(0, max_rules + 1, size=q)
     src, dst = distinct_targets(rng, q, deg)
-    rules = random_rules(rng, nr, dmax, kmax=kmax, mmax=mmax, pmax=pmax)
+    if general:
+        rules = general_rules(rng, nr, dmax, long_delays=long_delays)
+        rules = rules[rng.permutation(rules.shape[0])]
+    else:
+        rules = random_rules(rng, nr, dmax, kmax=kmax, mmax=mmax, pmax=pmax)
     spikes0 = rng.integers(0, c0max + 1, size=q).astype(np.int32)
     return SnpSpec("small%d" % seed, q, spikes0, rules, src, dst, select,
                    system_seed(seed, 7), steps)

@@ -36,6 +36,22 @@ def test_splitmix64_published_outputs():
         assert orc.mix64(int(state, 16)) == int(out, 16)
 
 
+def test_hash_choice_known_answers():
+    # the composition h(seed, k, i) and the multiply-shift pick, against known
+    # answers worked out from the published definitions (tests/golden)
+    n = 0
+    for ln in lines("hash_kat.txt"):
+        f = ln.split()
+        if f[0] == "mix64":
+            assert orc.mix64(int(f[1], 16)) == int(f[2], 16), ln
+        else:
+            seed, k, i, h = int(f[1]), int(f[2]), int(f[3]), int(f[4], 16)
+            assert orc.hash_key(seed, k, i) == h, ln
+            assert [orc.pick(h, a) for a in range(1, 5)] == [int(x) for x in f[5:9]], ln
+        n += 1
+    assert n == 7
+
+
 def test_pick_power_of_two_is_top_bits():
     # multiply-shift reduction: for a = 2^j the pick is the top j bits of h>>32
     rng = np.random.default_rng(0)
@@ -233,6 +249,11 @@ def _tiny_systems():
     rng = np.random.default_rng(5)
     for t in range(150):
         spec = wl.small_random(1000 + t, 3, max_deg=2, max_rules=3, dmax=2, c0max=4)
+        yield 3, spec.spikes0.tolist(), spec.rules.tolist(), spec.src.tolist(), spec.dst.tolist()
+    # every expression form, c unrelated to the expression, forgetting rules,
+    # delays, rule ids not grouped by neuron
+    for t in range(120):
+        spec = wl.small_random(2000 + t, 3, max_deg=2, max_rules=4, dmax=3, c0max=6, general=True)
         yield 3, spec.spikes0.tolist(), spec.rules.tolist(), spec.src.tolist(), spec.dst.tolist()
 
 
@@ -458,6 +479,85 @@ def _conservation_check(spec, sem, sel, steps):
         sel_rules = S[S >= 0]
         assert (spec.rules[sel_rules, 0] == np.nonzero(S >= 0)[0]).all()
         prev = C
+
+
+def _replay_counters(spec, sem, rec):
+    """Re-derives, from the recorded trajectory alone (C, D, S after every
+    step), the delays and the configuration of each step and every work
+    counter, with set operations over the synapse arrays (Sec. 2: selection
+    consumes c; STANDARD sends p when the delay expires, PAPER_KERNEL at
+    selection; only open targets receive).  Independent of the oracle's
+    step loop: nothing here calls it except through `rec`."""
+    q = spec.q
+    R = spec.rules.astype(np.int64)
+    nrules = np.bincount(R[:, 0], minlength=q) if spec.m else np.zeros(q, np.int64)
+    outdeg = np.bincount(spec.src, minlength=q).astype(np.int64)
+    indeg = np.bincount(spec.dst, minlength=q).astype(np.int64)
+    src, dst = spec.src.astype(np.int64), spec.dst.astype(np.int64)
+    Cp = spec.spikes0.astype(np.int64)
+    Dp = np.zeros(q, np.int64)
+    waiting = np.full(q, -1, np.int64)      # rule whose spikes a closed neuron still owes
+    for t in range(rec["steps"]):
+        C, D, S = rec["C"][t].astype(np.int64), rec["D"][t].astype(np.int64), rec["S"][t].astype(np.int64)
+        opened = Dp == 0
+        sel = S >= 0
+        assert not (sel & ~opened).any(), t            # only open neurons select
+        r = np.where(sel, S, 0)
+        p_sel = np.where(sel, R[r, 4], 0)
+        d_sel = np.where(sel, R[r, 5], 0)
+        c_sel = np.where(sel, R[r, 3], 0)
+        # delay counters: d on selection, count down while closed
+        assert np.array_equal(D, np.where(opened, d_sel, Dp - 1)), t
+        reopen = ~opened & (D == 0)
+        if sem == STD:
+            owed = np.where(reopen, R[np.where(waiting >= 0, waiting, 0), 4], 0)
+            emit = np.where(sel & (d_sel == 0), p_sel, 0) + owed
+            recv = D == 0
+            waiting = np.where(sel & (d_sel > 0), S, np.where(reopen, -1, waiting))
+        else:
+            emit = p_sel
+            recv = opened
+        val = emit[src]
+        into_open = recv[dst]
+        got = np.bincount(dst, weights=val * into_open, minlength=q).astype(np.int64) if spec.nnz else 0
+        assert np.array_equal(C, Cp - c_sel + got), t
+        emitting = emit > 0
+        want = {
+            "open_neurons": int(opened.sum()),
+            "rules_of_open": int(nrules[opened].sum()),
+            "selecting": int(sel.sum()),
+            "emitting": int(emitting.sum()),
+            "emit_edges": int(outdeg[emitting].sum()),
+            "spikes_sent": int((emit * outdeg).sum()),
+            "spikes_lost": int((val * ~into_open).sum()),
+            "receiving": int(recv.sum()),
+            "reopening": int(reopen.sum()),
+            "recv_in_edges": int(indeg[recv].sum()),
+        }
+        assert rec["counters"][t] == want, (t, rec["counters"][t], want)
+        Cp, Dp = C, D
+    return rec["steps"]
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_work_counters_replayed_config1(sem):
+    spec = wl.config1(steps=100)
+    assert _replay_counters(spec, sem, make(spec, sem).step_record(100)) == 100
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_work_counters_replayed_hash(sem, seed):
+    spec = wl.small_random(seed, 700, max_deg=7, max_rules=4, dmax=4, c0max=9, select=HASH)
+    assert _replay_counters(spec, sem, make(spec, sem).step_record(80)) > 20
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
+def test_work_counters_replayed_general_rules(sem):
+    # forgetting rules, c unrelated to the expression, long delays, shuffled ids
+    spec = wl.small_random(13, 600, max_deg=6, max_rules=5, dmax=15, c0max=12, select=HASH,
+                           general=True)
+    assert _replay_counters(spec, sem, make(spec, sem).step_record(80)) > 20
 
 
 @pytest.mark.parametrize("sem", [STD, PK])

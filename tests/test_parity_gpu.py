@@ -109,18 +109,73 @@ def test_periods_that_divide_every_step(binding, layout, rule_bytes):
     compare_every_step(binding, spec, layout, "paper_kernel", orc.SEM_PAPER_KERNEL, 30, rule_bytes=rule_bytes)
 
 
-def test_rule_records_fall_back_to_wider(binding):
-    # a field beyond the 4-byte format (c = 300, d = 20, p = 40) takes 8 bytes,
-    # beyond the 8-byte one (p = 300) 16 bytes
-    base = [(0, 1, 1, 1, 1, 0), (1, 1, 0, 1, 1, 0)]
-    for extra, width in (((0, 300, 0, 300, 1, 0), 8), ((0, 2, 0, 2, 1, 20), 8), ((0, 2, 0, 2, 40, 0), 8),
-                         ((0, 2, 0, 2, 300, 0), 16), ((0, 1500, 0, 1500, 1, 0), 8)):
-        g = binding.System(2, [3, 0], base + [extra], [0], [1])
-        assert g.info()["rule_bytes"] == width, extra
-        g.step(5)
-        o = orc.OracleSystem(2, [3, 0], base + [extra], [0], [1])
-        o.step(5)
-        assert g.read_config().tolist() == o.read()["C"].tolist()
+# A rule outside the 4-byte record (c = 300, lo = 1500, p = 40, d = 20) takes
+# 8 bytes, outside the 8-byte one (p = 300, d = 300) 16 bytes.  The wide rule
+# has the lowest id on neuron 0 and the count it needs, so it fires first.
+WIDE_RECORD_CASES = [((0, 300, 0, 300, 1, 0), 300, 8), ((0, 2, 0, 2, 1, 20), 2, 8), ((0, 2, 0, 2, 40, 0), 2, 8),
+                     ((0, 1500, 0, 1500, 1, 0), 1500, 8), ((0, 2, 0, 2, 300, 0), 2, 16),
+                     ((0, 2, 0, 2, 1, 300), 2, 16), ((0, 1, 1, 1, 2, 17), 4, 8)]
+
+
+@pytest.mark.parametrize("layout", ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "ell", "csr_push",
+                                    "sparse", "ell_atomic", "sliced_wide"])
+@pytest.mark.parametrize("case", range(len(WIDE_RECORD_CASES)))
+def test_rule_records_fall_back_to_wider(binding, layout, case):
+    extra, c0, width = WIDE_RECORD_CASES[case]
+    rules = np.array([extra, (0, 1, 1, 1, 1, 0), (1, 1, 0, 1, 1, 0), (2, 1, 1, 1, 1, 1)], np.int32)
+    spec = wl.SnpSpec("wide%d" % case, 3, np.array([c0, 0, 1], np.int32), rules,
+                      np.array([0, 0, 1, 2], np.int32), np.array([1, 2, 2, 0], np.int32))
+    steps = extra[5] + 8
+    g = gpu_of(binding, spec, layout, "standard")
+    assert g.info()["rule_bytes"] == width, extra
+    g.close()
+    for sem_name, sem in SEMS:
+        ref = oracle_of(spec, sem).step_record(steps)
+        assert ref["S"][0][0] == 0, "the wide rule fires at step 0"
+        compare_every_step(binding, spec, layout, sem_name, sem, steps)
+
+
+def _general_spec(seed, select, long_delays=0, q=3000):
+    return wl.small_random(seed, q, max_deg=7, max_rules=5, dmax=15, c0max=12, select=select, general=True,
+                           long_delays=long_delays)
+
+
+def _fired_delays(spec, sem, steps):
+    ref = oracle_of(spec, sem).step_record(steps)
+    S = ref["S"]
+    return set(spec.rules[S[S >= 0], 5].tolist())
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("select", ["first", "hash"])
+def test_general_rule_forms_every_step(binding, layout, select):
+    # every expression form (a^k, a^k(a^j)*, a*, a+, a^0), c below, at and
+    # above the expression's base, forgetting rules, delays up to 15, rule
+    # ids in shuffled order (not grouped by neuron)
+    sel = wl.SELECT_FIRST if select == "first" else wl.SELECT_HASH
+    spec = _general_spec(61 + sel, sel)
+    R = spec.rules
+    assert (np.diff(R[:, 0]) < 0).any(), "ids interleave neurons"
+    assert ((R[:, 1] == 0) & (R[:, 2] == 1)).any() and ((R[:, 3] > R[:, 1]) & (R[:, 2] > 0)).any()
+    assert ((R[:, 3] < R[:, 1])).any() and ((R[:, 3] > R[:, 1]) & (R[:, 2] == 0)).any()
+    assert max(_fired_delays(spec, orc.SEM_STANDARD, 40)) >= 12
+    g = gpu_of(binding, spec, layout, "standard")
+    assert g.info()["rule_bytes"] == 4
+    g.close()
+    for sem_name, sem in SEMS:
+        compare_every_step(binding, spec, layout, sem_name, sem, 40)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_long_delays_in_wider_records_every_step(binding, layout):
+    # delays 16..40 do not fit the 4-bit field of the 4-byte record: 8 bytes
+    spec = _general_spec(71, wl.SELECT_HASH, long_delays=60)
+    assert max(_fired_delays(spec, orc.SEM_STANDARD, 60)) > 15
+    g = gpu_of(binding, spec, layout, "standard")
+    assert g.info()["rule_bytes"] == 8
+    g.close()
+    for sem_name, sem in SEMS:
+        compare_every_step(binding, spec, layout, sem_name, sem, 60)
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -144,8 +199,17 @@ def test_hand_trace_h1(binding, layout):
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("sel,seed", [("first", 0), ("hash", 1)])
 def test_hand_trace_h2(binding, layout, sel, seed):
-    rules = [(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)]
+    # every step against the oracle (whose trace is pinned by hand), then
+    # the hand-traced end state: FIRST r1, r1; HASH (seed 1) r2, r0
+    rules = np.array([(0, 3, 0, 3, 1, 0), (0, 2, 2, 2, 1, 0), (0, 1, 1, 1, 1, 0), (0, 4, 0, 4, 1, 0)], np.int32)
+    selc = wl.SELECT_FIRST if sel == "first" else wl.SELECT_HASH
+    spec = wl.SnpSpec("h2", 1, np.array([4], np.int32), rules, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                      selc, seed)
+    assert compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 10) == 2
     g = binding.System(1, [4], rules, [], [], select=sel, seed=seed, **lk(layout))
+    g.step(1)
+    assert g.read_config().tolist() == ([2] if sel == "first" else [3])
+    assert g.read_spiking().tolist() == ([1] if sel == "first" else [2])
     g.step(10)
     assert g.steps_done() == (2, True)
     assert g.read_config().tolist() == [0]
@@ -691,10 +755,45 @@ def test_config2_full_size_digests(binding):
 @pytest.mark.parametrize("layout", ["optimized", "sliced", "ell", "csr_push", "csr_push_atomic"])
 def test_config2_full_size_push_layouts(binding, layout):
     spec = wl.config2(steps=40)
-    ref = oracle_of(spec, orc.SEM_STANDARD).step_record(40, want_state=False)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    ref = o.step_record(40, want_state=False)
     g = binding.System.from_spec(spec, **lk(layout), digest=True)
     g.step(40)
     assert np.array_equal(g.read_digests(0, 40), ref["digests"])
+    r = o.read()
+    assert np.array_equal(g.read_config(), r["C"])
+    assert np.array_equal(g.read_delays(), r["D"])
+    assert np.array_equal(g.read_spiking(), r["S"])
+    assert np.array_equal(g.read_pending(), r["pend"])
+
+
+@pytest.fixture(scope="module")
+def config3_case():
+    # the skewed workload at full size (4,194,304 neurons, power-law out-degree
+    # up to 4,096, in-degree hubs, delays up to 5, HASH) and the oracle's
+    # digests of its first 50 steps
+    spec = wl.config3(steps=50)
+    o = oracle_of(spec, orc.SEM_STANDARD)
+    ref = o.step_record(50, want_state=False)
+    r = o.read()
+    o.close()
+    return spec, ref, r
+
+
+@pytest.mark.parametrize("layout", ["csr_pull_gather", "csr_push", "sliced"])
+def test_config3_full_size_digests(binding, config3_case, layout):
+    spec, ref, r = config3_case
+    assert ref["steps"] == 50
+    g = binding.System.from_spec(spec, **lk(layout), digest=True)
+    if layout != "csr_pull_gather":
+        assert g.info()["push_mode"] == binding.PUSH_BINNED
+    g.step(50)
+    assert g.steps_done()[0] == 50
+    assert np.array_equal(g.read_digests(0, 50), ref["digests"])
+    assert np.array_equal(g.read_config(), r["C"])
+    assert np.array_equal(g.read_delays(), r["D"])
+    assert np.array_equal(g.read_spiking(), r["S"])
+    g.close()
 
 
 def test_config4_full_batch_sampled(binding):
