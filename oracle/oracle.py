@@ -50,11 +50,12 @@ COUNTER_FIELDS = [n for n, _ in Counters._fields_]
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc into ``libsnp_oracle.so`` (single-threaded)."""
+    """Compile the oracle with gcc into ``libsnp_oracle.so`` (with OpenMP for
+    orc_step_parallel; every other entry point runs on one thread)."""
     with _lock:
         if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             tmp = _LIB + ".tmp%d" % os.getpid()
-            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
                                    "-o", tmp, _SRC])
             os.replace(tmp, _LIB)
     return _LIB
@@ -112,6 +113,10 @@ def bind(lib):
     lib.orc_applicable.restype = ct.c_int32
     lib.orc_step_choice.argtypes = [ct.c_void_p, P(ct.c_int32)]
     lib.orc_step_choice.restype = ct.c_int
+    lib.orc_step_parallel.argtypes = [ct.c_void_p, ct.c_int64]
+    lib.orc_step_parallel.restype = ct.c_int64
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = ct.c_int
     return lib
 
 
@@ -125,6 +130,11 @@ def mix64(z: int) -> int:
 
 def hash_key(seed: int, k: int, i: int) -> int:
     return int(_load().orc_hash(seed & 0xFFFFFFFFFFFFFFFF, k, i))
+
+
+def threads() -> int:
+    """Threads orc_step_parallel uses (OpenMP's maximum)."""
+    return int(_load().orc_threads())
 
 
 def pick(h: int, a: int) -> int:
@@ -183,6 +193,13 @@ class OracleSystem:
 
     def step(self, n: int) -> int:
         return int(self._lib.orc_step(self._h, n))
+
+    def step_parallel(self, n: int) -> int:
+        """The same steps on all host cores (OpenMP; no work counters)."""
+        done = int(self._lib.orc_step_parallel(self._h, n))
+        if done < 0:
+            raise OracleError("orc_step_parallel: out of memory")
+        return done
 
     def set_synapses(self, src, dst):
         """Replaces the synapse set between steps (state kept)."""

@@ -413,6 +413,122 @@ int64_t orc_step(orc_sys* s, int64_t n) {
   return done;
 }
 
+/* ---- the same step on all host cores (CPU baseline) ------------------------
+ * Built with OpenMP, this runs the two phases of step_with in parallel:
+ * phase 1 per neuron (each neuron's selection, consumption, delay and
+ * emission touch only its own entries), phase 2 as a pull over in-lists
+ * (each target sums what its in-neighbours send, so no two threads write the
+ * same entry).  Same states as orc_step (checked by the tests); the work
+ * counters are not kept.  Without OpenMP the pragmas are ignored and it runs
+ * on one core. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* In-lists, built on first use: the sources of each target. */
+static int build_inlists(orc_sys* s, int32_t** istart_out, int32_t** ilist_out) {
+  const int32_t q = s->q;
+  int32_t* istart = (int32_t*)calloc((size_t)q + 1, sizeof(int32_t));
+  int32_t* ilist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->nsyn > 0 ? s->nsyn : 1));
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)q);
+  if (!istart || !ilist || !fill) { free(istart); free(ilist); free(fill); return -2; }
+  for (int32_t t = 0; t < q; ++t) istart[t + 1] = s->indeg[t];
+  for (int32_t t = 0; t < q; ++t) istart[t + 1] += istart[t];
+  for (int32_t t = 0; t < q; ++t) fill[t] = istart[t];
+  for (int32_t i = 0; i < q; ++i)
+    for (int32_t e = s->ostart[i]; e < s->ostart[i + 1]; ++e) ilist[fill[s->olist[e]]++] = i;
+  free(fill);
+  *istart_out = istart;
+  *ilist_out = ilist;
+  return 0;
+}
+
+/* Runs up to n steps on all host cores; returns the number executed, or -2
+ * if the in-lists cannot be allocated. */
+int64_t orc_step_parallel(orc_sys* s, int64_t n) {
+  int32_t *istart = NULL, *ilist = NULL;
+  if (build_inlists(s, &istart, &ilist) != 0) return -2;
+  const int32_t q = s->q;
+  int64_t done = 0;
+  while (done < n && !s->halted) {
+    /* the stop condition: some neuron closed, or an open one with an applicable rule */
+    int active = 0;
+#pragma omp parallel for reduction(|| : active) schedule(static)
+    for (int32_t i = 0; i < q; ++i) {
+      if (s->D[i] != 0) { active = 1; continue; }
+      for (int32_t j = s->rstart[i]; j < s->rstart[i + 1]; ++j)
+        if (applicable(&s->rules[s->rlist[j]], s->C[i])) { active = 1; break; }
+    }
+    if (!active) { s->halted = 1; break; }
+    /* phase 1: each neuron on its own (its applicable rules counted, then the
+     * chosen one found again, so no scratch is shared) */
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < q; ++i) {
+      int32_t sel_rule = -1;
+      s->cons[i] = 0;
+      s->emit[i] = 0;
+      if (s->D[i] == 0) {
+        int32_t na = 0;
+        for (int32_t j = s->rstart[i]; j < s->rstart[i + 1]; ++j)
+          if (applicable(&s->rules[s->rlist[j]], s->C[i])) na++;
+        if (na > 0) {
+          int32_t want = s->sel == ORC_SEL_FIRST ? 0 : (int32_t)orc_pick(orc_hash(s->seed, s->k, i), (uint32_t)na);
+          for (int32_t j = s->rstart[i]; j < s->rstart[i + 1]; ++j)
+            if (applicable(&s->rules[s->rlist[j]], s->C[i]) && want-- == 0) { sel_rule = s->rlist[j]; break; }
+        }
+        if (sel_rule >= 0) {
+          const orc_rule* r = &s->rules[sel_rule];
+          s->cons[i] = r->c;
+          if (s->sem == ORC_SEM_PAPER_KERNEL || r->d == 0) {
+            s->emit[i] = r->p;
+            s->Dn[i] = r->d;
+          } else {
+            s->Dn[i] = r->d;
+            s->pend[i] = sel_rule;
+          }
+        } else {
+          s->Dn[i] = 0;
+        }
+      } else {
+        s->Dn[i] = s->D[i] - 1;
+        if (s->sem == ORC_SEM_STANDARD && s->Dn[i] == 0) {
+          s->emit[i] = s->rules[s->pend[i]].p;
+          s->pend[i] = -1;
+        }
+      }
+      s->S[i] = sel_rule;
+      s->recv_open[i] = s->sem == ORC_SEM_STANDARD ? (s->Dn[i] == 0) : (s->D[i] == 0);
+    }
+    /* phase 2: every target pulls from its in-neighbours */
+    int ovf = 0;
+#pragma omp parallel for reduction(|| : ovf) schedule(static)
+    for (int32_t t = 0; t < q; ++t) {
+      int64_t got = 0;
+      if (s->recv_open[t])
+        for (int32_t e = istart[t]; e < istart[t + 1]; ++e) got += s->emit[ilist[e]];
+      s->C[t] = s->C[t] - s->cons[t] + got;
+      if (s->C[t] > INT32_MAX) ovf = 1;
+    }
+#pragma omp parallel for schedule(static)
+    for (int32_t t = 0; t < q; ++t) s->D[t] = s->Dn[t];
+    if (ovf) s->overflow = 1;
+    s->k++;
+    memset(&s->cnt, 0, sizeof(s->cnt));
+    done++;
+  }
+  free(istart);
+  free(ilist);
+  return done;
+}
+
 /* ---- branches of the computation (Sec. 2: a neuron with several applicable
  * rules uses one of them, chosen nondeterministically; the SAMPLE_ONE step of
  * Alg. 1 follows a single branch) ------------------------------------------ */

@@ -100,11 +100,16 @@ def test_unmutated_oracle_passes_every_pin():
 def test_every_planted_mistake_fails_a_pin(case, tmp_path):
     name, old, new = MUTATIONS[case]
     src = open(orc._SRC).read()
-    assert src.count(old) == 1, "the text to mutate must occur exactly once: %s" % name
+    # mistakes go into the plain step loop (the pins run it), not into its
+    # all-cores copy further down the file
+    a = src.index("/* ---- the same step on all host cores")
+    b = src.index("/* ---- branches of the computation")
+    rest = src[:a] + "\0" + src[b:]
+    assert rest.count(old) == 1, "the text to mutate must occur exactly once: %s" % name
     path = tmp_path / "mutant.c"
-    path.write_text(src.replace(old, new))
+    path.write_text(rest.replace(old, new).replace("\0", src[a:b]))
     so = str(tmp_path / ("mutant%d.so" % case))
-    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", so, str(path)])
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", so, str(path)])
     lib = orc.bind(ct.CDLL(so))
     assert _failing_pins(lib), "planted mistake not caught: %s" % name
     os.remove(so)

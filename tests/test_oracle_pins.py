@@ -561,6 +561,31 @@ def test_work_counters_replayed_general_rules(sem):
 
 
 @pytest.mark.parametrize("sem", [STD, PK])
+@pytest.mark.parametrize("case", ["config1", "hash", "general", "sort"])
+def test_parallel_steps_equal_plain_steps(sem, case):
+    # the all-cores build of the step (phase 2 as a pull over in-lists)
+    # reaches the same states as the plain two-phase loop
+    if case == "config1":
+        spec = wl.config1(steps=100)
+    elif case == "hash":
+        spec = wl.small_random(17, 3000, max_deg=9, max_rules=4, dmax=3, c0max=9, select=HASH)
+    elif case == "general":
+        spec = wl.small_random(18, 3000, max_deg=9, max_rules=5, dmax=15, c0max=12, select=HASH,
+                               general=True, long_delays=30)
+    else:
+        spec = wl.sort_system([5, 3, 9, 1, 7])
+    a, b = make(spec, sem), make(spec, sem)
+    for chunk in (1, 7, 40):
+        na, nb_ = a.step(chunk), b.step_parallel(chunk)
+        assert na == nb_
+        ra, rb = a.read(), b.read()
+        for key in ("C", "D", "S", "pend"):
+            assert np.array_equal(ra[key], rb[key]), (case, key)
+        assert a.digest() == b.digest()
+        assert a.halted == b.halted and a.steps_done == b.steps_done
+
+
+@pytest.mark.parametrize("sem", [STD, PK])
 def test_spike_conservation_config1(sem):
     _conservation_check(wl.config1(steps=100), sem, FIRST, 100)
 
