@@ -136,6 +136,11 @@ extern "C" {
                                  a time) instead of row by row as Table 3 is
                                  drawn ([z][q]: neighbouring neurons'
                                  entries side by side, the default)          */
+#define SNP_F_BIN_SPILL 0x80u /* binned push, for tests: each region keeps
+                                 only its record count in the block's LDS
+                                 stage, every record goes straight to device
+                                 memory (the path of regions whose share of
+                                 the stage is full)                           */
 #define SNP_F_ELL_ROWS 0x10u  /* ELL stored row by row as Table 2 is drawn
                                  ([z'][m]: a row contiguous over rules) instead
                                  of rule by rule ([m][z']: a rule's column

@@ -20,8 +20,8 @@ LAYOUT_AUTO, LAYOUT_OPTIMIZED, LAYOUT_ELL, LAYOUT_CSR_PUSH, LAYOUT_CSR_PULL, LAY
     0, 1, 2, 3, 4, 5, 6
 SELECT_FIRST, SELECT_HASH = 0, 1
 SEM_STANDARD, SEM_PAPER_KERNEL = 0, 1
-F_DIGEST, F_COUNTERS, F_NO_GRAPH, F_WIDE_RULES, F_ELL_ROWS, F_SY_COLUMNS, F_RULES8 = \
-    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
+F_DIGEST, F_COUNTERS, F_NO_GRAPH, F_WIDE_RULES, F_ELL_ROWS, F_SY_COLUMNS, F_RULES8, F_BIN_SPILL = \
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80
 
 LAYOUTS = {"auto": LAYOUT_AUTO, "optimized": LAYOUT_OPTIMIZED, "ell": LAYOUT_ELL,
            "csr_push": LAYOUT_CSR_PUSH, "csr_pull": LAYOUT_CSR_PULL, "sliced": LAYOUT_SLICED,
@@ -212,7 +212,7 @@ class System:
                  semantics="standard", seed=0, chunk=64, digest=False, counters=False,
                  graph=True, ring=0, device=None, memory="auto", stream=None, emit_bits=0,
                  wide_rules=False, pull_mode="auto", push_mode="auto", ell_rows=False, sy_columns=False,
-                 rule_bytes=0):
+                 rule_bytes=0, bin_spill=False):
         self._h = ct.c_void_p()
         self.q = int(q)
         s0 = _i32(spikes0)
@@ -231,7 +231,8 @@ class System:
         o.flags = ((F_DIGEST if digest else 0) | (F_COUNTERS if counters else 0) |
                    (0 if graph else F_NO_GRAPH) | (F_WIDE_RULES if wide_rules or rule_bytes == 16 else 0) |
                    (F_RULES8 if rule_bytes == 8 else 0) |
-                   (F_ELL_ROWS if ell_rows else 0) | (F_SY_COLUMNS if sy_columns else 0))
+                   (F_ELL_ROWS if ell_rows else 0) | (F_SY_COLUMNS if sy_columns else 0) |
+                   (F_BIN_SPILL if bin_spill else 0))
         o.ring = int(ring)
         o.emit_bits = int(emit_bits)
         o.pull_mode = PULL_MODES[pull_mode] if isinstance(pull_mode, str) else int(pull_mode)

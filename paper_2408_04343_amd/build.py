@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsnp.so")
 SOURCES = ["snp_api.hip", "snp_batch.hip", "snp_kernels.hip", "snp_step_pull.hip", "snp_step_pull_gather.hip",
-           "snp_step_pull_wide.hip", "snp_step_bin.hip",
+           "snp_step_pull_wide.hip", "snp_step_bin.hip", "snp_step_bin_csr.hip", "snp_step_bin_sy.hip",
            "snp_step_push.hip", "snp_tree.hip"]
 ARCH = os.environ.get("SNP_OFFLOAD_ARCH", "gfx950")
 

@@ -146,14 +146,16 @@ int64_t plan_bytes(int32_t q, int32_t m, int64_t nnz, int32_t z, int32_t layout,
     p.add(24LL * q + 16);    // wide schedule: choices, many-rule list, emitter list and counts
     p.add(4LL * (q + 1));    // out_ptr
     const int64_t nb = (q + (1LL << BIN_TB) - 1) >> BIN_TB;
-    if (nb <= BIN_MAX_TILES) {  // binned push: bins, counts, region offsets
-      p.add(4LL * std::max<int64_t>(nnz, 1));
-      p.add(4LL * std::max<int64_t>(nnz, 1));
-      for (int x = 0; x < 4; ++x) p.add(4LL * nb * nb);
+    p.add(2LL * q);            // out-degrees
+    if (nb <= BIN_MAX_TILES) {  // binned push: two bin buffers, region offsets and stage shares
+      // a region holds at most one 16-byte chunk beyond its 4-byte records
+      for (int x = 0; x < 2; ++x) p.add(4LL * std::max<int64_t>(nnz, 1) + 32LL * nb * nb + 16);
+      p.add(4LL * nb * (nb + 1));
+      for (int x = 0; x < 2; ++x) p.add(4LL * nb * nb);
     }
-    p.add(4LL * std::max<int64_t>(nnz, 1));
+    p.add(4LL * std::max<int64_t>(nnz, 1) + 16);
     if (layout == L_OPT) p.add(4LL * ((z + 3) & ~3) * q);
-    if (layout == L_SPARSE) p.add(4LL * std::max(m, 1) * q);
+    if (layout == L_SPARSE) p.add(4LL * std::max(m, 1) * q + 16);
     if (layout == L_SLICED) {  // at most the global height, at most 64 slots per synapse
       const int64_t ns = (q + SLICE - 1) / SLICE;
       p.add(8 * (ns + 1));
@@ -329,14 +331,12 @@ int alloc_state(snp_sys* s, const int32_t* spikes0) {
       if ((st = alloc_fill(s, (void**)&d.ecnt, 16, 0)) != SNP_OK) return st;
     }
     d.bins[0] = d.bins[1] = nullptr;
-    d.bcnt[0] = d.bcnt[1] = nullptr;
     if (d.push_binned) {
-      const size_t nb2 = (size_t)d.bnb * (size_t)d.bnb;
-      for (int b = 0; b < 2; ++b) {
-        d.bins[b] = (uint32_t*)s->dalloc(4 * (size_t)std::max<int64_t>(s->nnz, 1));
-        if (!d.bins[b]) return fail(SNP_ENOMEM, "device allocation failed");
-        if ((st = alloc_fill(s, (void**)&d.bcnt[b], 4 * nb2, 0)) != SNP_OK) return st;
-      }
+      // every region's count is written by the step that fills the buffer;
+      // zeroed so that a read before any step finds empty regions
+      for (int b = 0; b < 2; ++b)
+        if ((st = alloc_fill(s, (void**)&d.bins[b], 16 * (size_t)std::max<int64_t>(s->bchunks, 1), 0)) != SNP_OK)
+          return st;
     }
   }
   return SNP_OK;
@@ -723,32 +723,92 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       d.n_heavy = (int32_t)hv.size();
     }
     if (d.push_binned) {
-      // region (b -> t) holds one slot per synapse from tile b into tile t;
-      // regions are laid out target-major, so a tile's inbox is contiguous
-      std::vector<int32_t> cap((size_t)(nb * nb), 0);
+      // region (b -> t): its record count, then one record slot per synapse
+      // from tile b into tile t, in 16-byte chunks; regions are laid out
+      // target-major, so a tile's inbox is contiguous.  Records take two
+      // bytes when every value sent is below 16.
+      d.brec = pmax_all < 16 ? 2 : 4;
+      const int64_t R = 16 / d.brec, H = 4 / d.brec;
+      std::vector<int64_t> cap((size_t)(nb * nb), 0);
       for (int32_t i = 0; i < q; ++i)
         for (int32_t e = op[i]; e < op[(size_t)i + 1]; ++e)
           cap[(size_t)((oc[e] >> BIN_TB) * nb + (i >> BIN_TB))]++;   // [t][b]
-      std::vector<int32_t> offc((size_t)(nb * nb)), offp((size_t)(nb * nb));
+      std::vector<int32_t> offc((size_t)(nb * (nb + 1))), offp((size_t)(nb * nb), -1);
+      std::vector<int64_t> chunks((size_t)(nb * nb), 0);                  // [b][t]
       int64_t run = 0;
-      for (int64_t t = 0; t < nb; ++t)
+      for (int64_t t = 0; t < nb; ++t) {
         for (int64_t b = 0; b < nb; ++b) {
-          offc[(size_t)(t * nb + b)] = (int32_t)run;
-          offp[(size_t)(b * nb + t)] = (int32_t)run;
-          run += cap[(size_t)(t * nb + b)];
+          const int64_t c = cap[(size_t)(t * nb + b)];
+          const int64_t n = c > 0 ? (c + H + R - 1) / R : 0;
+          offc[(size_t)(t * (nb + 1) + b)] = (int32_t)run;
+          if (c > 0) offp[(size_t)(b * nb + t)] = (int32_t)run;
+          chunks[(size_t)(b * nb + t)] = n;
+          run += n;
+          if (run > 0x7FFFFFFFLL) return bail(fail(SNP_ENOTSUP, "bin buffer beyond 2^31 chunks"));
         }
+        offc[(size_t)(t * (nb + 1) + nb)] = (int32_t)run;
+      }
+      s->bchunks = run;
+      // each source tile's regions share the block's LDS stage: the whole
+      // region when they all fit, else shares proportional to the regions'
+      // sizes, at least the count chunk each (records past a share go
+      // straight to device memory)
+      const int64_t SC = bin_stage_chunks((int32_t)nb);
+      std::vector<uint32_t> stg((size_t)(nb * nb), 0);
+      int32_t full = 1;
+      for (int64_t b = 0; b < nb; ++b) {
+        int64_t sum = 0, nne = 0;
+        for (int64_t t = 0; t < nb; ++t) {
+          sum += chunks[(size_t)(b * nb + t)];
+          nne += chunks[(size_t)(b * nb + t)] > 0;
+        }
+        int64_t base = 0;
+        for (int64_t t = 0; t < nb; ++t) {
+          const int64_t n = chunks[(size_t)(b * nb + t)];
+          if (n == 0) continue;
+          int64_t lc = sum <= SC ? n : 1 + (n - 1) * (SC - nne) / (sum - nne);
+          if (o.flags & SNP_F_BIN_SPILL) lc = 1;
+          lc = std::min<int64_t>(lc, 0xFFFF);
+          if (lc < n) full = 0;
+          stg[(size_t)(b * nb + t)] = (uint32_t)base | ((uint32_t)lc << 16);
+          base += lc;
+        }
+      }
+      d.bfull = full;
       if ((st = upload(s, &p, offc.data(), offc.size())) != SNP_OK) return bail(st);
       d.boff = p;
       if ((st = upload(s, &p, offp.data(), offp.size())) != SNP_OK) return bail(st);
       d.boffp = p;
+      uint32_t* pu;
+      if ((st = upload(s, &pu, stg.data(), stg.size())) != SNP_OK) return bail(st);
+      d.bstg = pu;
+      static std::atomic<uint64_t> bin_ready{0};  // one bit per device
+      const uint64_t bit = 1ull << (s->dev & 63);
+      if (!(bin_ready.load() & bit)) {
+        if (prepare_bin_kernels() != hipSuccess)
+          return bail(fail(SNP_EDEVICE, "cannot raise the LDS limit of the binned kernels"));
+        bin_ready.fetch_or(bit);
+      }
+    }
+    {
+      std::vector<uint16_t> d16((size_t)q);
+      for (int32_t i = 0; i < q; ++i) d16[i] = (uint16_t)std::min(op[(size_t)i + 1] - op[i], 0xFFFF);
+      uint16_t* pd;
+      if ((st = upload(s, &pd, d16.data(), d16.size())) != SNP_OK) return bail(st);
+      d.deg16 = pd;
     }
     if ((st = upload(s, &p, op.data(), (size_t)q + 1)) != SNP_OK) return bail(st);
     d.out_ptr = p;
-    if ((st = upload(s, &p, oc.data(), (size_t)nsyn)) != SNP_OK) return bail(st);
+    {
+      // rows are read in 16-byte pieces: the array ends on a whole piece
+      std::vector<int32_t> ocp(oc.begin(), oc.begin() + nsyn);
+      ocp.resize((size_t)((nsyn + 3) / 4 * 4 + 4), -1);
+      if ((st = upload(s, &p, ocp.data(), ocp.size())) != SNP_OK) return bail(st);
+    }
     d.out_col = p;
     if (o.layout == SNP_LAYOUT_SPARSE) {
       int32_t* dense = nullptr;
-      if ((st = alloc_fill(s, (void**)&dense, 4 * (size_t)std::max(m, 1) * (size_t)q, 0)) != SNP_OK)
+      if ((st = alloc_fill(s, (void**)&dense, 4 * (size_t)std::max(m, 1) * (size_t)q + 16, 0)) != SNP_OK)
         return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "the dense matrix does not fit in device memory") : st);
       d.dense = dense;
       if (hipSuccess != launch_build_dense(d, dense, s->stream)) return bail(fail(SNP_EDEVICE, "build_dense"));
@@ -811,6 +871,7 @@ int snp_clone(snp_sys* base, const int32_t* spikes0, uint64_t seed, void* stream
   s->m = root->m;
   s->z = root->z;
   s->nnz = root->nnz;
+  s->bchunks = root->bchunks;
   s->layout = root->layout;
   s->chunk = root->chunk;
   s->base = root;
@@ -1009,7 +1070,7 @@ int snp_write_state(snp_sys* s, const int32_t* C, const int32_t* D, const int32_
     for (int b = 0; b < 2; ++b) HIPCHK(hipMemsetAsync(s->d.delta[b], 0, 4 * (size_t)q, s->stream));
     if (s->d.push_binned)
       for (int b = 0; b < 2; ++b)
-        HIPCHK(hipMemsetAsync(s->d.bcnt[b], 0, 4 * (size_t)s->d.bnb * (size_t)s->d.bnb, s->stream));
+        HIPCHK(hipMemsetAsync(s->d.bins[b], 0, 16 * (size_t)std::max<int64_t>(s->bchunks, 1), s->stream));
     if (s->d.push_wide) HIPCHK(hipMemsetAsync(s->d.ecnt, 0, 16, s->stream));
   }
   Ctl c;

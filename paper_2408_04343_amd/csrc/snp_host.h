@@ -39,6 +39,7 @@ struct snp_sys {
   snp::SysDev d{};
   int32_t q = 0, m = 0, z = 0, layout = 0;
   int64_t nnz = 0;
+  int64_t bchunks = 0;                   // 16-byte chunks of one bin buffer (binned push)
   std::vector<void*> allocs;
   std::vector<int32_t> h_rid, h_slot, h_rs, h_out_ptr, h_out_col, h_in_ptr, h_in_src;
   int32_t* scratch = nullptr;            // [4][q] materialized C, D, S, pend

@@ -23,6 +23,21 @@ constexpr int32_t PULL_TB_GATHER = 10;  // log2 neurons per pull tile, gather re
 constexpr int32_t SEL_LIGHT_RULES = 32;  // rules a thread scans alone; more: a wave per neuron
 constexpr int32_t BIN_TB = 12;          // log2 neurons per tile of the binned push
 constexpr int32_t BIN_MAX_TILES = 2048; // binned push up to 2048 tiles (8,388,608 neurons)
+constexpr int32_t BIN_LDS_BYTES = 159 * 1024;  // dynamic LDS of one binned block
+constexpr int32_t BIN_HMAX = 256;       // long rows a binned block walks together
+constexpr int32_t BIN_WAVES = 16;       // waves of a binned block
+constexpr int32_t BIN_WL = 3 * 64;      // LDS words of one wave's list of rows
+
+// LDS of a binned block, in 4-byte words: offp[nb] | lcnt[nb] | stg[nb] |
+// (even) long-row list [BIN_HMAX][4] | row lists [BIN_WAVES][BIN_WL] | from
+// bin_union_word on, the reception and selection arrays, later the stage
+// of outgoing records (bin_stage_chunks 16-byte chunks).
+__host__ __device__ inline int32_t bin_union_word(int32_t nb) {
+  return ((((3 * nb + 1) & ~1) + 4 * BIN_HMAX + BIN_WAVES * BIN_WL) + 3) & ~3;
+}
+__host__ __device__ inline int32_t bin_stage_chunks(int32_t nb) {
+  return (BIN_LDS_BYTES / 4 - bin_union_word(nb)) / 4;
+}
 constexpr int32_t PUSH_LIGHT = 32;      // wide push: row entries a thread walks alone
 
 // One rule of the rule vector RV in neuron order (16 bytes).
@@ -96,15 +111,22 @@ struct SysDev {
   const int32_t* out_col;    // CSR_PUSH: [nnz]
   const int32_t* out_deg;    // counters only: [q]
   const int32_t* in_deg;     // counters only, push layouts: [q]
-  // binned push: spikes travel as records (target offset | value << 12) in
-  // regions (source tile b -> target tile t) of 4096-neuron tiles; a region
-  // holds as many slots as there are synapses from b into t
+  // binned push: spikes travel as records (target offset | value << 12, of
+  // brec bytes) in regions (source tile b -> target tile t) of 4096-neuron
+  // tiles.  A region is a run of 16-byte chunks: its record count in the
+  // first 4 bytes, then one record slot per synapse from b into t; regions
+  // without a synapse take no chunk.  Regions of one target tile are
+  // contiguous.
   int32_t push_binned;       // 1: binned reception, 0: atomic adds into delta
   int32_t bnb;               // tiles (at most 2048)
-  uint32_t* bins[2];         // [max(nnz, 1)] records sent at step k, by k & 1
-  int32_t* bcnt[2];          // [bnb][bnb] records in region (b -> t), stored at [t][b], by k & 1
-  const int32_t* boff;       // [bnb][bnb] first slot of region (b -> t), stored at [t][b]
-  const int32_t* boffp;      // [bnb][bnb] the same, stored at [b][t]
+  int32_t brec;              // bytes per record: 2 when every value is below 16, else 4
+  int32_t bfull;             // 1: every region of every tile fits its stage in LDS
+  uint4* bins[2];            // [bchunks] regions written at step k, by k & 1
+  const int32_t* boff;       // [bnb][bnb + 1] first chunk of region (b -> t), stored at [t][b]
+  const int32_t* boffp;      // [bnb][bnb] the same (-1: no synapse), stored at [b][t]
+  const uint32_t* bstg;      // [bnb][bnb] stage of region (b -> t) in tile b's LDS, in
+                             //   chunks: first | count << 16, stored at [b][t]
+  const uint16_t* deg16;     // [q] out-degree, 65535 = read out_ptr
   // wide push: many-rule neurons choose by waves (hsel, heavy below); rows
   // longer than PUSH_LIGHT entries are listed and walked by one wave each
   int32_t push_wide;
@@ -166,6 +188,7 @@ hipError_t launch_step_bin_batch(const SysDev& s, const SysDev* members, const i
 // Sums the records of buffer rbuf per target into out[q] (binned push).
 hipError_t launch_bin_gather(const SysDev& s, int32_t rbuf, int32_t* out, hipStream_t st);
 size_t bin_lds_bytes(const SysDev& s);
+hipError_t prepare_bin_kernels();
 hipError_t launch_advance(Ctl* ctl, int32_t n, hipStream_t st);
 // Batched form: one launch steps every member; `proto` supplies the shared
 // kernel choice (layout, widths, flags), `members`/`tiles`/`ntiles` live in

@@ -18,12 +18,16 @@ pytestmark = pytest.mark.gpu
 # device-wide atomic adds, "*_wide" the wide push schedule (waves choose
 # among many rules and walk long rows)
 LAYOUTS = ["csr_pull", "csr_pull_gather", "csr_pull_wide", "optimized", "optimized_columns", "sliced", "ell",
-           "ell_rows", "csr_push", "sparse", "optimized_atomic", "sliced_atomic", "ell_atomic", "csr_push_atomic",
-           "sparse_atomic", "optimized_wide", "sliced_wide", "ell_wide", "csr_push_wide", "sparse_wide"]
+           "ell_rows", "csr_push", "sparse", "ell_spill", "optimized_atomic", "sliced_atomic", "ell_atomic",
+           "csr_push_atomic", "sparse_atomic", "optimized_wide", "sliced_wide", "ell_wide", "csr_push_wide",
+           "sparse_wide"]
 
 
 def lk(layout):
-    """System keyword arguments of a test layout name."""
+    """System keyword arguments of a test layout name ("*_spill": binned push
+    whose records bypass the LDS stage, see SNP_F_BIN_SPILL)."""
+    if layout.endswith("_spill"):
+        return dict(lk(layout[:-len("_spill")]), push_mode="binned", bin_spill=True)
     if layout in ("csr_pull_gather", "csr_pull_wide"):
         return {"layout": "csr_pull", "pull_mode": layout[len("csr_pull_"):]}
     if layout.endswith("_atomic"):
@@ -441,13 +445,31 @@ def _heavy_spec(n_heavy, hub_deg, q=6000, seed=21):
                       wl.SELECT_HASH, 5, 12)
 
 
-@pytest.mark.parametrize("layout", ["optimized", "sliced", "ell", "csr_push"])
+@pytest.mark.parametrize("layout", ["optimized", "optimized_columns", "sliced", "ell", "ell_rows", "csr_push"])
 @pytest.mark.parametrize("n_heavy", [40, 1100])
-def test_binned_heavy_rows(binding, layout, n_heavy):
-    # rows longer than a thread walks alone go to the block; more heavy
-    # neurons than the block's list holds are walked by their threads
+@pytest.mark.parametrize("spill", [False, True])
+def test_binned_heavy_rows(binding, layout, n_heavy, spill):
+    # rows longer than a thread (strided layouts) or a wave (contiguous ones)
+    # walks alone go to the block; more long rows than the block's list
+    # holds are walked by their threads
     spec = _heavy_spec(n_heavy, 2500)
-    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 12, push_mode="binned")
+    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 12, push_mode="binned",
+                       bin_spill=spill)
+
+
+@pytest.mark.parametrize("layout", ["optimized", "optimized_columns", "sliced", "ell", "ell_rows", "csr_push",
+                                    "sparse"])
+@pytest.mark.parametrize("pmax", [2, 40])
+@pytest.mark.parametrize("spill", [False, True])
+def test_binned_records_every_step(binding, layout, pmax, spill):
+    # records of two bytes (every value below 16) or four (values up to 40),
+    # staged in LDS or, with spill, past each region's count chunk written
+    # straight to device memory; three tiles and a ragged tail
+    spec = wl.small_random(81 + pmax, 9000, max_deg=12, max_rules=3, dmax=3, c0max=10, pmax=pmax,
+                           select=wl.SELECT_HASH)
+    assert (spec.rules[:, 4].max() >= 16) == (pmax >= 16)
+    compare_every_step(binding, spec, layout, "standard", orc.SEM_STANDARD, 25, push_mode="binned",
+                       bin_spill=spill)
 
 
 def test_push_auto_mode_choice(binding):
