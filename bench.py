@@ -22,38 +22,50 @@ sys.path.insert(0, ROOT)
 
 METRIC = "neuron-updates/s + HBM GB/s (% peak), batched vs plain; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = ("config2-large: 1,048,576 neurons, Poisson(16) out-degree (cap 64), 1-4 rules/neuron, "
-            "delays 0..3, initial spikes U{0..8}, lowest-index rule, 1,000 steps")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes of one step, from the exact per-step work counters.
-# Shared by every layout (state): C read+write, meta (D + reception flag)
-# read+write, 16-bit spiking record written, rule offsets read, the rule
-# records (R bytes each) of open neurons read, pending rule read/written
-# around reopening.
-def state_bytes(q, c, rule_bytes):
-    return 8 * q + 8 * q + 2 * q + 4 * q + rule_bytes * c["rules_of_open"] + 8 * c["reopening"]
-
-
-def layout_bytes(layout, q, c, emit_w):
+# Algorithmic bytes of one step: what the method must move, from the exact
+# per-step work counters of the same trajectory (G = out-edges of emitting
+# neurons, E = emitting neurons, R = bytes per rule record).
+#   state, every layout: q * (4 C read + 4 C write + 4 D read + 4 D write
+#     + 4 S write + 4 neuron-rule map read + 8 receive buffer read/reset)
+#     + 8 per reopening neuron (pending rule) + R per rule of an open neuron;
+#   ELL: 8 (G + E), the (neuron, value) pairs of the emitting rules' columns,
+#     rows 0..deg;  Optimized / sliced Sy: 4 G;  CSR push: 4 G + 4 E (targets
+#     and row offsets);  pull: 4 per in-edge of an open target + 4q (in-list
+#     offsets) + 4q (emit buffer).
+def alg_bytes(layout, q, c, rule_bytes):
     G, E = c["emit_edges"], c["emitting"]
-    if layout == "csr_pull":
-        # in-list offsets, in-lists of receiving neurons, emitted values written + read once
-        return 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
-    push = 8 * q + 4 * G          # receive buffer read + cleared, one 4-byte update per delivery
-    if layout in ("optimized", "optimized_columns", "sliced"):
-        return push + 4 * (G + E)     # Sy entries of emitters (+ terminator)
-    if layout == "ell":
-        return push + 8 * (G + E)     # (neuron, value) pairs of emitting rules (+ terminator)
-    return push + 4 * G + 8 * E       # csr_push: targets + row bounds
+    state = 32 * q + 8 * c["reopening"] + rule_bytes * c["rules_of_open"]
+    base = layout.split("_spill")[0]
+    if base == "csr_pull":
+        return state + 4 * c["recv_in_edges"] + 8 * q
+    if base == "ell":
+        return state + 8 * (G + E)
+    if base in ("optimized", "optimized_columns", "sliced"):
+        return state + 4 * G
+    return state + 4 * G + 4 * E    # csr_push
 
 
-def step_bytes(layout, q, c, info):
-    return state_bytes(q, c, info["rule_bytes"]) + layout_bytes(layout, q, c, info["emit_bits"])
+# The same step counted with the packed encodings the kernels use (16-bit
+# spiking record, W-bit emitted values, no receive buffer in the pull form),
+# reported beside the algorithmic figure.
+def packed_bytes(layout, q, c, rule_bytes, emit_w):
+    G, E = c["emit_edges"], c["emitting"]
+    state = 8 * q + 8 * q + 2 * q + 4 * q + rule_bytes * c["rules_of_open"] + 8 * c["reopening"]
+    base = layout.split("_spill")[0]
+    if base == "csr_pull":
+        return state + 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
+    push = 8 * q + 4 * G
+    if base in ("optimized", "optimized_columns", "sliced"):
+        return state + push + 4 * (G + E)
+    if base == "ell":
+        return state + push + 8 * (G + E)
+    return state + push + 4 * G + 8 * E
 
 
 def layout_kwargs(layout):
@@ -64,10 +76,10 @@ def layout_kwargs(layout):
     return {"layout": layout}
 
 
-def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
+def run_layout(binding, torch, spec, layout, steps, warmup, chunk, **kw):
     """Times `steps` steps after `warmup` on one system; returns a result dict."""
     t0 = time.time()
-    g = binding.System.from_spec(spec, chunk=chunk, **layout_kwargs(layout))
+    g = binding.System.from_spec(spec, chunk=chunk, **layout_kwargs(layout), **kw)
     create_s = time.time() - t0
     info = g.info()
     stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
@@ -96,19 +108,29 @@ def run_layout(binding, torch, spec, layout, steps, warmup, chunk):
             "step_ms_p99": float(np.percentile(full, 99)) if full else per_step_ms}
 
 
-def count_bytes(binding, spec, layout, steps, warmup, info):
-    g = binding.System.from_spec(spec, counters=True, ring=max(4096, steps + 8), **layout_kwargs(layout))
+def count_bytes(binding, spec, layout, steps, warmup, info, **kw):
+    """Mean algorithmic and packed bytes per step over steps warmup ..
+    warmup + steps - 1 of the same trajectory, and the counters."""
+    g = binding.System.from_spec(spec, counters=True, ring=max(4096, steps + 8), **layout_kwargs(layout), **kw)
     g.step(warmup + steps)
     cnt = g.read_counters(warmup, steps)
     g.close()
-    b = [step_bytes(layout, spec.q, c, info) for c in cnt]
-    return float(np.mean(b)), cnt
+    a = [alg_bytes(layout, spec.q, c, info["rule_bytes"]) for c in cnt]
+    p = [packed_bytes(layout, spec.q, c, info["rule_bytes"], info["emit_bits"]) for c in cnt]
+    return float(np.mean(a)), float(np.mean(p)), cnt
 
 
-def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0):
-    """Config 4: n independent systems (sizes log-uniform 1,000-262,144), one
-    batched launch per step vs the same systems stepped one after another.
-    Both time steps warmup..warmup+steps from the same initial states."""
+def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0, cpu_seconds=0.0,
+                counters=True):
+    """Config 4: n independent systems (sizes log-uniform 1,000-262,144).  Every
+    member is built in the two batchable pull schedules (LDS-staged and
+    gathered emitted values); the tuner times the whole batch for several
+    size thresholds (members below it staged, the others gathered) and keeps
+    the fastest.  Then, from the same initial states, the tuned batch (one
+    launch per step and schedule) is timed against the same members stepped
+    one after another, and the forced all-staged / all-gathered batches are
+    timed too."""
+    from paper_2408_04343_amd import tune
     from paper_2408_04343_amd import workloads as wl
     t0 = time.time()
     sizes = wl.config4_sizes(4, n)
@@ -116,98 +138,159 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
         sizes = np.maximum(1000, (sizes * scale).astype(np.int64))
     specs = [wl.config4_system(j, int(sizes[j]), 4, steps) for j in range(n)]
     gen_s = time.time() - t0
-    # the tuner's choice on the smallest, the median and the largest member
-    from paper_2408_04343_amd import tune
-    order = np.argsort(sizes)
-    tuned = {}
-    for j in (order[0], order[n // 2], order[-1]):
-        ch = tune.tune(specs[j], layout="csr_pull", steps=64, emit_bits=2)
-        tuned[int(sizes[j])] = {"choice": ch.mode, "auto": ch.auto,
-                                "us_per_step": {k: round(v, 2) for k, v in ch.us_per_step.items()}}
-        log("tuner, member of %d neurons: %s (auto %s) %s" % (sizes[j], ch.mode, ch.auto, ch.us_per_step))
     stream = torch.cuda.Stream()
     total_q = int(sum(sp.q for sp in specs))
     nu = total_q * steps
-    modes = {}
-    plain_ms = plain_digest = None
-    create_s = 0.0
-    for mode in ("auto", "staged", "gather"):
-        t0 = time.time()
-        systems = [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2, pull_mode=mode,
-                                            stream=stream.cuda_stream) for sp in specs]
-        if mode == "auto":
-            create_s = time.time() - t0
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        if plain_ms is None:
-            # plain: each system alone, one after another on one stream
-            for g in systems:
-                g.step(warmup)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for g in systems:
-                g.step(steps)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            plain_ms = e0.elapsed_time(e1)
-            plain_digest = [g.digest() for g in systems]
-            # back to the initial states for the batched run
-            for sp, g in zip(specs, systems):
-                g.write_state(sp.spikes0, np.zeros(sp.q, np.int32), None, None, 0)
-        # batched: one launch per step and reception mode for all systems
-        b = binding.Batch(systems, chunk=chunk, capacity_members=n,
-                          capacity_tiles=sum((sp.q + 1023) // 1024 for sp in specs))
+    t0 = time.time()
+    built = {m: [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2, pull_mode=m,
+                                          stream=stream.cuda_stream) for sp in specs]
+             for m in ("staged", "gather")}
+    create_s = time.time() - t0
+    cap_tiles = sum((sp.q + 1023) // 1024 for sp in specs)
+    choice = tune.tune_batch(built["staged"], built["gather"], steps=64, warmup=16, chunk=chunk,
+                             capacity_tiles=cap_tiles)
+    log("batch tuner: %s (ms per 64 steps: %s)" % (tune.threshold_label(choice.threshold), choice.ms))
+    chosen = [a if choice.mode_of(a.q) == "staged" else b for a, b in zip(built["staged"], built["gather"])]
+
+    def reset(systems):
+        for sp, g in zip(specs, systems):
+            g.write_state(sp.spikes0, np.zeros(sp.q, np.int32), None, None, 0)
+
+    def time_batch(members):
+        reset(members)
+        b = binding.Batch(members, chunk=chunk, capacity_members=n, capacity_tiles=cap_tiles)
         b.step(warmup)
         b.sync()
         bs = b.stream if b.stream is not None else stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(bs)
         b.step(steps)
         e1.record(bs)
         torch.cuda.synchronize()
-        batch_ms = e0.elapsed_time(e1)
         ntiles = b.size()[1]
         b.close()
-        same = all(g.digest() == d for g, d in zip(systems, plain_digest))
-        ngather = sum(1 for g in systems if g.info()["pull_mode"] == binding.PULL_GATHER)
-        for g in systems:
+        return e0.elapsed_time(e1), ntiles, [g.digest() for g in members]
+
+    # plain: the tuned members alone, one after another on one stream
+    reset(chosen)
+    for g in chosen:
+        g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for g in chosen:
+        g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_digest = [g.digest() for g in chosen]
+    batch_ms, ntiles, dig = time_batch(chosen)
+    same = dig == plain_digest
+    forced = {}
+    for m in ("staged", "gather"):
+        ms, nt, d = time_batch(built[m])
+        forced[m] = {"ms": ms, "neuron_updates_per_s": nu / (ms * 1e-3), "tiles": nt,
+                     "equals_plain": d == plain_digest}
+    log("batched %d systems (%d neurons, tuned %s, %d tiles): %.2f ms vs plain sequential %.2f ms, digests %s; "
+        "forced staged %.2f ms, gather %.2f ms" % (n, total_q, tune.threshold_label(choice.threshold), ntiles,
+                                                  batch_ms, plain_ms, "equal" if same else "DIFFERENT",
+                                                  forced["staged"]["ms"], forced["gather"]["ms"]))
+    roof = None
+    if counters:
+        # exact algorithmic bytes of the batched step: every member's counters
+        # over the same steps (members built with counters, run as one batch)
+        cs = [binding.System.from_spec(sp, layout="csr_pull", chunk=chunk, emit_bits=2, counters=True,
+                                       ring=max(4096, warmup + steps + 8), pull_mode=choice.mode_of(sp.q),
+                                       stream=stream.cuda_stream) for sp in specs]
+        b = binding.Batch(cs, chunk=chunk, capacity_members=n, capacity_tiles=cap_tiles)
+        b.step(warmup + steps)
+        b.sync()
+        b.close()
+        per_step = np.zeros(steps)
+        for sp, g in zip(specs, cs):
+            cnt = g.read_counters(warmup, steps)
+            info = g.info()
+            per_step += np.array([alg_bytes("csr_pull", sp.q, c, info["rule_bytes"]) for c in cnt])
             g.close()
-        modes[mode] = {"ms": batch_ms, "neuron_updates_per_s": nu / (batch_ms * 1e-3), "tiles": ntiles,
-                       "gather_members": ngather, "equals_plain": bool(same)}
-        log("batched %d systems (%d neurons, %s: %d gather members, %d tiles): %.2f ms vs plain sequential "
-            "%.2f ms, digests %s" % (n, total_q, mode, ngather, ntiles, batch_ms, plain_ms,
-                                     "equal" if same else "DIFFERENT"))
-    best = min(modes, key=lambda m: modes[m]["ms"])
+        ab = float(per_step.mean())
+        gbps = ab / (batch_ms / steps * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "step_pull_batch_kernel (staged and gather launches of one step)",
+                "alg_bytes_per_launch": round(ab), "avg_launch_us": round(1e3 * batch_ms / steps, 3)}
+    cpu = None
+    if cpu_seconds > 0:
+        cpu = cpu_baseline_sample(specs, cpu_seconds)
+    for m in built.values():
+        for g in m:
+            g.close()
     return {"workload": "config4-batched: %d systems, sizes log-uniform 1,000-262,144 (total %d "
                         "neurons), Poisson(12) out-degree, 1-4 rules, delays 0..3, hash choice, "
-                        "%d timed steps" % (n, total_q, steps),
-            "systems": n, "neurons": total_q, "steps": steps, "tiles": modes["auto"]["tiles"],
-            "batched": {"ms": modes["auto"]["ms"], "neuron_updates_per_s": modes["auto"]["neuron_updates_per_s"]},
-            "batched_by_mode": modes, "fastest_mode": best,
+                        "%d timed steps after %d warmup" % (n, total_q, steps, warmup),
+            "systems": n, "neurons": total_q, "steps": steps, "tiles": ntiles,
+            "batched": {"ms": batch_ms, "neuron_updates_per_s": nu / (batch_ms * 1e-3),
+                        "schedule": {"staged_below_q": choice.threshold, "label": tune.threshold_label(choice.threshold),
+                                     "staged_members": sum(1 for a in chosen if a in built["staged"])}},
+            "batched_forced": forced,
             "plain_sequential": {"ms": plain_ms, "neuron_updates_per_s": nu / (plain_ms * 1e-3)},
-            "speedup": plain_ms / modes["auto"]["ms"],
-            "batched_equals_plain": all(m["equals_plain"] for m in modes.values()),
+            "speedup": plain_ms / batch_ms,
+            "batched_equals_plain": bool(same and all(f["equals_plain"] for f in forced.values())),
+            "roofline": roof, "cpu_baseline": cpu,
             "gen_s": round(gen_s, 1), "create_s": round(create_s, 1),
-            "tuner": {"note": "measured schedule choice (graph of 64 steps per candidate) on the "
-                              "smallest, median and largest member, each alone", "members": tuned}}
+            "tuner": {"note": "every size threshold timed on the whole batch (64 steps after 16 warmup); "
+                              "members below it take the staged pull, the others the gathered one",
+                      "ms_per_64_steps": {k: round(v, 3) for k, v in choice.ms.items()}}}
 
 
-def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64, pull_mode="gather"):
+def cpu_baseline_sample(specs, seconds):
+    """The oracle (OpenMP build) on a sample of config-4 members: every 16th
+    by size, each for a few steps, about `seconds` in all."""
+    from oracle import oracle as orc
+    order = np.argsort([sp.q for sp in specs])
+    sample = [specs[j] for j in order[::16]]
+    per = seconds / max(1, len(sample))
+    nu = 0
+    t0 = time.time()
+    for sp in sample:
+        o = orc.OracleSystem(sp.q, sp.spikes0, sp.rules, sp.src, sp.dst, orc.SEM_STANDARD, sp.select, sp.seed)
+        t1 = time.time()
+        while time.time() - t1 < per:
+            got = o.step_parallel(5)
+            nu += sp.q * got
+            if got < 5:
+                break
+        o.close()
+    dt = time.time() - t0
+    return {"value": nu / dt, "unit": "neuron-updates/s", "cores": orc.threads(), "kind": "oracle",
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "sample": "config4: %d members (every 16th by size), OpenMP C oracle, %.1f s" % (len(sample), dt)}
+
+
+def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, tick=64, pull_mode="gather",
+               check_every=97, check_max_work=2e7):
     """Config 5: Poisson arrivals of requests with q ~ logU[1,000, 1,048,576]
-    and steps ~ logU[100, 10,000], hash choice.  Each request clones the
-    template nearest to its size (log scale), so a pool of templates stands in
-    for 120k distinct systems.  Runs at `rate` req/s and, if capacity_nu is
-    given, again at 0.7x the capacity it implies."""
+    and steps ~ logU[100, 10,000], hash choice.  Each request is a clone (own
+    state and HASH key, shared structure) of the template nearest to its
+    size (log scale): a pool of templates stands in for 120k distinct
+    systems.  Admission charges each template in use its device footprint
+    once and each request its clone's bytes, as the library reports them.
+    Runs at `rate` req/s and, if capacity_nu is given, again at 0.7x the
+    capacity it implies.  Every `check_every`-th completed request of at most
+    `check_max_work` neuron-steps has its final state digest compared with
+    the oracle's run of the same system, key and step count."""
     from paper_2408_04343_amd import serve
     from paper_2408_04343_amd import workloads as wl
     t0 = time.time()
     tq = np.unique(np.round(np.exp(np.linspace(np.log(1000), np.log(1 << 20), n_templates))).astype(int))
     stream = torch.cuda.Stream()
+    tspecs = [wl.config5_system(1000 + j, int(q), 0, 0) for j, q in enumerate(tq)]
     # every request runs batched, where reading emitted values from device
     # memory (gather) is the fastest pull schedule measured (config 4)
-    templates = [binding.System.from_spec(wl.config5_system(1000 + j, int(q), 0, 0), emit_bits=2,
-                                          pull_mode=pull_mode, stream=stream.cuda_stream)
-                 for j, q in enumerate(tq)]
+    templates = [binding.System.from_spec(sp, emit_bits=2, pull_mode=pull_mode, stream=stream.cuda_stream)
+                 for sp in tspecs]
     prep_s = time.time() - t0
     logq = np.log(tq)
+    tidx = {id(t): j for j, t in enumerate(templates)}
 
     def make(rate_, dur, seed):
         arr, q, steps, seeds = wl.config5_requests(seed=seed, rate=rate_, duration=dur)
@@ -218,21 +301,34 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     def one(rate_, dur, seed):
         reqs = make(rate_, dur, seed)
         mean_work = float(np.mean([r.q * r.steps for r in reqs])) if reqs else 0.0
-        srv = serve.Server(tick_steps=tick, chunk=tick, max_members=256, max_tiles=8192)
+        sampled = []
+
+        def on_done(req, sysg):
+            if req.rid % check_every == 0 and req.q * req.steps <= check_max_work:
+                sampled.append((tidx[id(req.template)], req.seed, req.steps, req.steps_done, sysg.digest()))
+
+        srv = serve.Server(tick_steps=tick, chunk=tick, max_members=256, max_tiles=16384, on_done=on_done)
         st = srv.run(reqs, duration=dur)
         srv.close()
         st.update({"rate_req_per_s": rate_, "duration_s": dur,
                    "offered_neuron_updates_per_s": rate_ * mean_work})
-        log("served at %.0f req/s for %.0f s: %d/%d completed, %.3e nu/s, p50 %s s, p99 %s s" %
+        st["oracle_checked"] = served_check(tspecs, sampled)
+        log("served at %.0f req/s for %.0f s: %d/%d completed, %.3e nu/s, p50 %s s, p99 %s s "
+            "(wait p99 %s s, service p99 %s s); oracle sample %s" %
             (rate_, dur, st["completed"], st["arrived"], st["completed_neuron_updates_per_s"],
-             st["latency_p50_s"], st["latency_p99_s"]))
+             st["latency_p50_s"], st["latency_p99_s"], st["wait_p99_s"], st["service_p99_s"],
+             st["oracle_checked"]))
         return st, mean_work
 
     over, mean_work = one(rate, seconds, 5)
-    out = {"workload": "config5-served: Poisson arrivals, q ~ logU[1,000, 1,048,576] (nearest of %d "
-                       "templates), steps ~ logU[100, 10,000], Poisson(16) out-degree, hash choice"
-                       % len(tq),
-           "templates": len(tq), "template_pull_mode": pull_mode, "template_prep_s": round(prep_s, 1), "tick_steps": tick,
+    out = {"workload": "config5-served: Poisson arrivals, q ~ logU[1,000, 1,048,576], steps ~ logU[100, "
+                       "10,000], Poisson(16) out-degree, hash choice; each request a clone (own state and "
+                       "key) of the nearest of %d templates" % len(tq),
+           "templates": len(tq), "template_pull_mode": pull_mode, "template_prep_s": round(prep_s, 1),
+           "tick_steps": tick,
+           "note": "requests are clones of templates spanning the size range (shared structure, own "
+                   "state, key and step count), not distinct systems; admission charges templates in use "
+                   "and clones by the bytes the library reports",
            "at_rate": over}
     if capacity_nu:
         sub_rate = 0.7 * capacity_nu / mean_work
@@ -242,8 +338,42 @@ def run_served(binding, torch, rate, seconds, capacity_nu=None, n_templates=24, 
     return out
 
 
+def served_check(tspecs, sampled):
+    """Oracle runs of sampled served requests (template, key, steps): the
+    final digest and the executed steps must equal the served ones."""
+    from oracle import oracle as orc
+    ok = 0
+    for j, seed, steps, done, dig in sampled:
+        sp = tspecs[j]
+        o = orc.OracleSystem(sp.q, sp.spikes0, sp.rules, sp.src, sp.dst, orc.SEM_STANDARD, sp.select, seed)
+        o.step(steps)
+        ok += int(o.steps_done() == done and o.digest() == dig)
+        o.close()
+    return {"checked": len(sampled), "equal": ok}
+
+
+def skewed_check(binding, spec, layouts, steps):
+    """Digests of the first `steps` states of config 3 under each layout
+    against the oracle's (the oracle runs them on one host thread)."""
+    from oracle import oracle as orc
+    t0 = time.time()
+    o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
+                         spec.select, spec.seed)
+    ref = [int(x) for x in o.step_record(steps, want_state=False)["digests"]]
+    o.close()
+    oracle_s = time.time() - t0
+    res = {}
+    for lay in layouts:
+        g = binding.System.from_spec(spec, digest=True, **layout_kwargs(lay))
+        g.step(steps)
+        res[lay] = bool([int(x) for x in g.read_digests(0, steps)] == ref)
+        g.close()
+    log("config3 digests of %d steps vs oracle (%.1f s): %s" % (steps, oracle_s, res))
+    return {"steps": steps, "equal_to_oracle": res, "oracle_s": round(oracle_s, 1)}
+
+
 def run_skewed(binding, torch, steps=500, warmup=16,
-               layouts=("csr_pull", "optimized", "optimized_columns", "sliced", "csr_push")):
+               layouts=("csr_pull", "optimized", "optimized_columns", "sliced", "csr_push"), check_steps=20):
     """Config 3: 4,194,304 neurons, power-law out-degree (exponent 2.1, 1..4,096),
     in-degree hubs, hash choice, 500 steps.  ELL is reported analytically (its
     padded matrix, (z+1) x m pairs, exceeds the device memory)."""
@@ -274,13 +404,28 @@ def run_skewed(binding, torch, steps=500, warmup=16,
             out["layouts"][lay] = {"error": str(e)}
             log("config3 %s: %s" % (lay, e))
             continue
-        b, _cnt = count_bytes(binding, spec, lay, min(steps, 200), warmup, r["info"])
-        r["alg_bytes_per_step"] = b
-        r["alg_GBps"] = b / (r["ms_per_step"] * 1e-3) / 1e9
+        a, pk, _cnt = count_bytes(binding, spec, lay, min(steps, 200), warmup, r["info"])
+        r["alg_bytes_per_step"] = a
+        r["packed_bytes_per_step"] = pk
+        r["alg_GBps"] = a / (r["ms_per_step"] * 1e-3) / 1e9
+        r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
         r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+        r["kernel"] = step_kernel(lay, r["info"])
         out["layouts"][lay] = {k: v for k, v in r.items() if k != "info"}
-        log("config3 %-10s %.4f ms/step  %.3e nu/s  %.0f GB/s alg" %
-            (lay, r["ms_per_step"], r["neuron_updates_per_s"], r["alg_GBps"]))
+        log("config3 %-10s %.4f ms/step  %.3e nu/s  %.0f GB/s alg (%.3f of peak)" %
+            (lay, r["ms_per_step"], r["neuron_updates_per_s"], r["alg_GBps"], r["frac_of_peak"]))
+    ok = {k: v for k, v in out["layouts"].items() if "frac_of_peak" in v}
+    for tag, keys in (("roofline_pull", [k for k in ok if k == "csr_pull"]),
+                      ("roofline_push", [k for k in ok if k != "csr_pull"])):
+        if keys:
+            best = min(keys, key=lambda k: ok[k]["ms_per_step"])
+            v = ok[best]
+            out[tag] = {"bound": "hbm", "achieved": round(v["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(v["frac_of_peak"], 4), "traffic": None,
+                        "kernel": v["kernel"], "layout": best, "alg_bytes_per_launch": round(v["alg_bytes_per_step"]),
+                        "avg_launch_us": round(v["ms_per_step"] * 1e3, 3)}
+    if check_steps > 0:
+        out["parity"] = skewed_check(binding, spec, [k for k in ok], check_steps)
     return out
 
 
@@ -383,17 +528,67 @@ def run_ratios(binding, torch, n=500, layouts=RATIO_LAYOUTS):
     return out
 
 
-def cpu_baseline(spec, seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec, seconds, parallel=False):
+    """The oracle as it stands, timed on the host for about `seconds` on the
+    first steps of the workload: single-threaded, or its OpenMP build of the
+    same two phases (phase 1 per neuron, phase 2 as a pull over in-lists) on
+    every core OpenMP is given."""
     from oracle import oracle as orc
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
                          spec.select, spec.seed)
     n = 0
     t0 = time.time()
     while time.time() - t0 < seconds:
-        n += o.step(5)
+        got = o.step_parallel(5) if parallel else o.step(5)
+        n += got
+        if got < 5:
+            break
     dt = time.time() - t0
-    return {"value": spec.q * n / dt, "unit": "neuron-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%s: first %d steps, single-threaded C oracle (%.1f s)" % (spec.name, n, dt)}
+    o.close()
+    cores = orc.threads() if parallel else 1
+    return {"value": spec.q * n / dt, "unit": "neuron-updates/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "sample": "%s: first %d steps, %s C oracle (%.1f s)" %
+                      (spec.name, n, "OpenMP (%d threads)" % cores if parallel else "single-threaded", dt)}
+
+
+def call_latency(binding, torch, spec, layout, calls=200, warmup=16, **kw):
+    """p50 / p99 of single snp_step(1) calls on a resident system: host wall
+    time from the call to the end of its step (stream synchronized), and the
+    GPU time between events recorded around the call."""
+    g = binding.System.from_spec(spec, **layout_kwargs(layout), **kw)
+    stream = g._torch_stream if g._torch_stream is not None else torch.cuda.ExternalStream(g.stream)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    host, gpu = [], []
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for x in range(calls):
+        e[x][0].record(stream)
+        t0 = time.perf_counter()
+        g.step(1)
+        e[x][1].record(stream)
+        stream.synchronize()
+        host.append((time.perf_counter() - t0) * 1e6)
+    gpu = [a.elapsed_time(b) * 1e3 for a, b in e]
+    done, halted = g.steps_done()
+    g.close()
+    return {"layout": layout, "calls": calls, "steps_done": int(done), "halted": bool(halted),
+            "host_us_p50": round(float(np.percentile(host, 50)), 2),
+            "host_us_p99": round(float(np.percentile(host, 99)), 2),
+            "gpu_us_p50": round(float(np.percentile(gpu, 50)), 2),
+            "gpu_us_p99": round(float(np.percentile(gpu, 99)), 2),
+            "neuron_updates_per_s_p50": spec.q / (float(np.percentile(gpu, 50)) * 1e-6)}
 
 
 _COMMON = ["paper_2408_04343_amd/csrc/snp_device.h", "paper_2408_04343_amd/csrc/snp_internal.h"]
@@ -534,7 +729,11 @@ def main():
     ap.add_argument("--ratio-n", type=int, default=500,
                     help="sorting instance of the Sparse/ELL/Optimized comparison (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--skewed-check-steps", type=int, default=20,
+                    help="config-3 steps whose digests are compared with the oracle's")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--write-traffic", nargs=4, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "LAYOUT"),
                     help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the traffic file of a layout")
@@ -550,6 +749,7 @@ def main():
               "(no collectives); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import dataclasses
     import torch
     from paper_2408_04343_amd import binding
     from paper_2408_04343_amd import workloads as wl
@@ -562,49 +762,65 @@ def main():
     layouts = [x for x in args.layouts.split(",") if x]
     if args.layout not in layouts:
         layouts.insert(0, args.layout)
-    results = {}
-    for lay in layouts:
-        r = run_layout(binding, torch, spec, lay, args.steps, args.warmup, args.chunk)
+    copy_gbps = copy_bandwidth(torch)
+    log("copy bandwidth %.0f GB/s" % copy_gbps)
+
+    def measure(sp, lay, **kw):
+        r = run_layout(binding, torch, sp, lay, args.steps, args.warmup, args.chunk, **kw)
         if not args.no_counters:
-            b, cnt = count_bytes(binding, spec, lay, args.steps, args.warmup, r["info"])
-            r["alg_bytes_per_step"] = b
-            r["alg_GBps"] = b / (r["ms_per_step"] * 1e-3) / 1e9
+            a, pk, cnt = count_bytes(binding, sp, lay, args.steps, args.warmup, r["info"], **kw)
+            r["alg_bytes_per_step"] = a
+            r["packed_bytes_per_step"] = pk
+            r["alg_GBps"] = a / (r["ms_per_step"] * 1e-3) / 1e9
             r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
-            if lay == args.layout:
-                r["mean_counters"] = {k: float(np.mean([c[k] for c in cnt])) for k in cnt[0]}
-        r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+            r["packed_frac_of_peak"] = pk / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+            r["alg_frac_of_copy"] = r["alg_GBps"] / copy_gbps
+            r["mean_counters"] = {k: float(np.mean([c[k] for c in cnt])) for k in cnt[0]}
+        r["neuron_updates_per_s"] = sp.q / (r["ms_per_step"] * 1e-3)
         r["kernel"] = step_kernel(lay, r["info"])
         tb, _t = measured_traffic(r["kernel"], lay)
         if tb is not None:
             r["traffic_bytes_per_step"] = tb
             r["measured_GBps"] = tb / (r["ms_per_step"] * 1e-3) / 1e9
             r["measured_frac_of_peak"] = r["measured_GBps"] / HBM_PEAK_GBS
-        results[lay] = r
-        log("%-10s %.4f ms/step  %.3e nu/s  %s" % (lay, r["ms_per_step"], r["neuron_updates_per_s"],
-                                                   "%.0f GB/s alg" % r["alg_GBps"] if "alg_GBps" in r else ""))
+            r["measured_frac_of_copy"] = r["measured_GBps"] / copy_gbps
+        log("%-10s %-5s %.4f ms/step  %.3e nu/s  %s" %
+            (lay, "hash" if sp.select == wl.SELECT_HASH else "first", r["ms_per_step"], r["neuron_updates_per_s"],
+             "%.0f GB/s alg (%.3f of peak)" % (r["alg_GBps"], r["frac_of_peak"]) if "alg_GBps" in r else ""))
+        return r
+
+    def roof(r):
+        if "alg_GBps" not in r:
+            return None
+        t = r.get("traffic_bytes_per_step")
+        return {"bound": "hbm", "achieved": round(r["alg_GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(r["frac_of_peak"], 4), "traffic": None if t is None else int(t),
+                "kernel": r["kernel"], "layout": r["layout"],
+                "alg_bytes_per_launch": round(r["alg_bytes_per_step"]),
+                "avg_launch_us": round(r["ms_per_step"] * 1e3, 3),
+                "packed_bytes_per_launch": round(r["packed_bytes_per_step"]),
+                "packed_frac": round(r["packed_frac_of_peak"], 4),
+                "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(r["alg_frac_of_copy"], 4)}
+
+    results = {lay: measure(spec, lay) for lay in layouts}
+    # the same system with the hash choice (configs 3-5 use it)
+    spec_h = dataclasses.replace(spec, select=wl.SELECT_HASH, name="config2-large-hash")
+    results_hash = {lay: measure(spec_h, lay) for lay in [args.layout, "ell"] if lay in layouts}
     head = results[args.layout]
     value = spec.q * args.steps / (head["total_ms"] * 1e-3)
-    roof = None
-    traffic = head.get("traffic_bytes_per_step")
-    copy_gbps = copy_bandwidth(torch)
-    log("copy bandwidth %.0f GB/s" % copy_gbps)
-    for r in results.values():
-        if "alg_GBps" in r:
-            r["alg_frac_of_copy"] = r["alg_GBps"] / copy_gbps
-        if "measured_GBps" in r:
-            r["measured_frac_of_copy"] = r["measured_GBps"] / copy_gbps
-    if "alg_GBps" in head:
-        roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(head["frac_of_peak"], 4),
-                "traffic": None if traffic is None else int(traffic),
-                "kernel": head["kernel"],
-                "copy_GBps": round(copy_gbps, 1),
-                "alg_bytes_per_launch": round(head["alg_bytes_per_step"]),
-                "avg_launch_us": round(head["ms_per_step"] * 1e3, 3)}
+    # per-call latency of single steps: config 1 (launch-bound) and config 2
+    latency = {}
+    if not args.no_latency:
+        c1 = wl.config1()
+        for name, sp, lays in (("config1", c1, ("csr_pull", "ell")), ("config2", spec, (args.layout, "ell"))):
+            for lay in dict.fromkeys(lays):
+                latency["%s_%s" % (name, lay)] = call_latency(binding, torch, sp, lay, calls=args.latency_calls)
+                log("latency %s %s: %s" % (name, lay, latency["%s_%s" % (name, lay)]))
     batched = None
     if not args.no_batch:
-        batched = run_batched(binding, torch, scale=args.batch_scale)
-    skewed = None if args.no_skewed else run_skewed(binding, torch)
+        batched = run_batched(binding, torch, scale=args.batch_scale,
+                              cpu_seconds=0.0 if args.no_cpu else args.cpu_seconds / 2)
+    skewed = None if args.no_skewed else run_skewed(binding, torch, check_steps=args.skewed_check_steps)
     sort_sizes = [int(x) for x in args.sort_n.split(",") if x]
     sorting = run_sort(binding, torch, sort_sizes) if sort_sizes else None
     ratios = None if args.ratio_n <= 0 else run_ratios(binding, torch, args.ratio_n)
@@ -612,33 +828,47 @@ def main():
     if not args.no_serve:
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
         served = run_served(binding, torch, args.serve_rate, args.serve_seconds, capacity_nu=cap)
-    cpu = None
+    cpu = cpu_par = None
     if not args.no_cpu:
-        log("cpu baseline (oracle) for ~%.0f s ..." % args.cpu_seconds)
+        log("cpu baseline (oracle) for ~%.0f s single-threaded, ~%.0f s OpenMP ..." %
+            (args.cpu_seconds, args.cpu_seconds))
         cpu = cpu_baseline(spec, args.cpu_seconds)
+        cpu_par = cpu_baseline(spec, args.cpu_seconds, parallel=True)
+        log("cpu baseline: %s | %s" % (cpu, cpu_par))
+    rl = lambda d: {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in d.items()}
     out = {
         "metric": METRIC, "value": value, "unit": "neuron-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "q": spec.q, "rules": spec.m, "synapses": spec.nnz,
-                   "max_out_degree": spec.max_outdeg(), "layout": args.layout, "select": "first",
-                   "semantics": "standard", "graph_chunk": args.chunk,
+        "config": {"workload": workload_label(spec, args.steps, args.warmup), "q": spec.q, "rules": spec.m,
+                   "synapses": spec.nnz, "max_out_degree": spec.max_outdeg(), "layout": args.layout,
+                   "select": "first", "semantics": "standard", "graph_chunk": args.chunk,
                    "pull_tile_log2": head["info"].get("pull_tile_log2"),
                    "rule_bytes": head["info"].get("rule_bytes")},
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "roofline": roof(head),
+        "roofline_ell": roof(results["ell"]) if "ell" in results else None,
+        "cpu_baseline": cpu_par if cpu_par is not None else cpu,
+        "cpu_baseline_single_thread": cpu,
+        "hash_choice": rl(results_hash),
+        "latency_per_call": latency,
         "batched_vs_plain": batched,
         "served": served,
         "skewed": skewed,
         "sorting_family": sorting,
         "layout_ratios": ratios,
-        "latency_ms_per_step": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
-                                "over": "graph chunks of %d steps" % args.chunk},
-        "layouts": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()
-                        if kk != "mean_counters"} for k, v in results.items()},
+        "latency_ms_per_step_chunks": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
+                                       "over": "graph chunks of %d steps (mean per step)" % args.chunk},
+        "layouts": rl(results),
     }
     print(json.dumps(out), flush=True)
+
+
+def workload_label(spec, steps, warmup):
+    return ("config2-large: %s neurons, Poisson(16) out-degree (cap 64), 1-4 rules/neuron, delays 0..3, "
+            "initial spikes U{0..8}, lowest-index rule; %d timed steps after %d warmup" %
+            (format(spec.q, ","), steps, warmup))
 
 
 if __name__ == "__main__":

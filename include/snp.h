@@ -343,8 +343,12 @@ typedef struct snp_info_t {
   int32_t pull_chunks;   /* CSR_PULL: number of source chunks                */
   int32_t pull_mode;     /* CSR_PULL: SNP_PULL_STAGED, _GATHER or _WIDE      */
   int32_t push_mode;     /* push layouts: SNP_PUSH_ATOMIC, _BINNED or _WIDE  */
-  int32_t reserved;
+  int32_t step_tile;     /* neurons per block of its step kernel (the unit
+                            of a batch's tile capacity)                      */
   int64_t device_bytes;  /* device memory held by the handle                 */
+  int64_t clone_bytes;   /* device memory snp_clone allocates for a clone of
+                            this handle (its state arrays; the representation
+                            is shared)                                      */
 } snp_info_t;
 int snp_info(snp_sys* sys, snp_info_t* out);
 

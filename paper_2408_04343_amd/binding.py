@@ -78,7 +78,7 @@ class Info(ct.Structure):
                 ("layout", ct.c_int32), ("rule_bytes", ct.c_int32), ("emit_bits", ct.c_int32),
                 ("pull_tile_log2", ct.c_int32), ("pull_chunk", ct.c_int32),
                 ("pull_chunks", ct.c_int32), ("pull_mode", ct.c_int32), ("push_mode", ct.c_int32),
-                ("reserved", ct.c_int32), ("device_bytes", ct.c_int64)]
+                ("step_tile", ct.c_int32), ("device_bytes", ct.c_int64), ("clone_bytes", ct.c_int64)]
 
 
 class SnpError(RuntimeError):
@@ -378,7 +378,7 @@ class System:
     def info(self):
         i = Info()
         _check(lib.snp_info(self._h, ct.byref(i)))
-        return {n: int(getattr(i, n)) for n, _ in Info._fields_ if n != "reserved"}
+        return {n: int(getattr(i, n)) for n, _ in Info._fields_}
 
     def clone(self, seed=None, spikes0=None, stream=None):
         """A new system sharing this one's rules and synapses on the device."""

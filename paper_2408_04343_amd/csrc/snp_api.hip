@@ -847,7 +847,9 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       if (hipSuccess != launch_build_ell(d, ell, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
     }
   }
+  const int64_t structure_bytes = s->device_bytes;
   if ((st = alloc_state(s, spikes0)) != SNP_OK) return bail(st);
+  s->state_bytes = s->device_bytes - structure_bytes;
   if (hipStreamSynchronize(s->stream) != hipSuccess)
     return bail(fail(SNP_EDEVICE, std::string("create: ") + hipGetErrorString(hipGetLastError())));
   *out = s;
@@ -881,6 +883,7 @@ int snp_clone(snp_sys* base, const int32_t* spikes0, uint64_t seed, void* stream
   DevScope ds(s->dev);
   s->stream = stream ? (hipStream_t)stream : root->stream;
   int st = alloc_state(s, spikes0 ? spikes0 : root->h_spikes0.data());
+  s->state_bytes = s->device_bytes;
   if (st == SNP_OK && hipStreamSynchronize(s->stream) != hipSuccess)
     st = fail(SNP_EDEVICE, std::string("clone: ") + hipGetErrorString(hipGetLastError()));
   if (st != SNP_OK) {
@@ -1204,8 +1207,9 @@ int snp_info(snp_sys* s, snp_info_t* o) {
                  : s->d.pull_gather ? SNP_PULL_GATHER : SNP_PULL_STAGED;
   o->push_mode = s->layout == SNP_LAYOUT_CSR_PULL ? 0 : s->d.push_binned ? SNP_PUSH_BINNED
                      : s->d.push_wide ? SNP_PUSH_WIDE : SNP_PUSH_ATOMIC;
-  o->reserved = 0;
+  o->step_tile = step_tile(s->d);
   o->device_bytes = s->device_bytes;
+  o->clone_bytes = s->state_bytes;
   return SNP_OK;
 }
 

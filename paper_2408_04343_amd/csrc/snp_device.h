@@ -247,6 +247,52 @@ __device__ __forceinline__ bool step_prologue(const SysDev& s, int32_t tile, int
   return true;
 }
 
+// The fields of the control block that step_prologue reads, loaded one by
+// one at the start of a kernel (none of them is written by the launch that
+// reads them), so that their load overlaps the loads of the tile's state.
+struct CtlSnap {
+  int64_t k_base, k_limit;
+  int32_t halted, a0, a1, a2;
+};
+
+__device__ __forceinline__ CtlSnap ctl_snap(const Ctl* ctl) {
+  CtlSnap c;
+  c.k_base = ctl->k_base;
+  c.k_limit = ctl->k_limit;
+  c.halted = ctl->halted;
+  c.a0 = ctl->active[0];
+  c.a1 = ctl->active[1];
+  c.a2 = ctl->active[2];
+  return c;
+}
+
+// step_prologue on a snapshot taken by ctl_snap.
+__device__ __forceinline__ bool step_prologue_snap(const SysDev& s, const CtlSnap& c, int32_t tile, int32_t j,
+                                                   int64_t& k) {
+  Ctl* ctl = s.ctl;
+  k = c.k_base + j;
+  if (c.halted || k >= c.k_limit) return false;
+  // active[(k - 1) mod 3] as a bit of a mask (a select over the fields
+  // would be turned back into an indexed copy in scratch memory)
+  const uint32_t act = (uint32_t)(c.a0 != 0) | ((uint32_t)(c.a1 != 0) << 1) | ((uint32_t)(c.a2 != 0) << 2);
+  const bool prev = (act >> (uint32_t)((k + 2) % 3)) & 1u;
+  if (k > 0 && !prev) {
+    if (tile == 0 && threadIdx.x == 0) {
+      ctl->halt_step = k - 1;
+      ctl->halted = 1;
+    }
+    return false;
+  }
+  if (tile == 0 && threadIdx.x == 0) {
+    ctl->active[(k + 1) % 3] = 0;
+    ctl->k_exec = k + 1;
+    if (s.flags & F_DIGEST) s.digests[k % s.ring] = 0;
+    if (s.flags & F_COUNTERS)
+      for (int x = 0; x < NCOUNT; ++x) s.counters[((k + 1) % s.ring) * NCOUNT + x] = 0;
+  }
+  return true;
+}
+
 // Would step k = k_base + j run?  The same test as step_prologue, read-only:
 // for the launches around a step kernel (they see the same answer before
 // and after it, since the step kernel only sets `halted` when it skips).

@@ -51,6 +51,7 @@ struct snp_sys {
   int in_batch = 0;
   hipStream_t batch_stream = nullptr;   // stream of the batch the handle is in
   int64_t device_bytes = 0;
+  int64_t state_bytes = 0;              // device bytes of the state arrays (what a clone allocates)
   snp_sys* base = nullptr;              // clones: the handle whose structure they share
   int clones = 0;                       // live clones sharing this handle's structure
   std::vector<int32_t> h_spikes0;       // C_0, for clones without their own

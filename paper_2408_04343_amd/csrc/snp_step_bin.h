@@ -494,8 +494,10 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
   const int32_t t0 = tile * BIN_TILE;
   const int tid = threadIdx.x;
 
-  // the tile's state and the static row data are loaded before the step
-  // index (their addresses do not depend on it), so that the latencies overlap
+  // the control block, the tile's state and the static row data are loaded
+  // before any of them is used (no address depends on the step index), so
+  // that their latencies overlap
+  const CtlSnap cs = ctl_snap(s.ctl);
   NeuronIn<RB> in[BIN_NPT];
   uint32_t d16[BIN_NPT];
   int32_t rstart[BIN_NPT];
@@ -522,7 +524,7 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
     L.lcnt[b] = (int32_t)(sg & 0xFFFFu) * R + H;
   }
   int64_t k;
-  if (!step_prologue(s, tile, j, k)) return;
+  if (!step_prologue_snap(s, cs, tile, j, k)) return;
 #pragma unroll
   for (int r = 0; r < BIN_NPT; ++r) L.acc[tid + r * BIN_NT] = 0;
   if (tid == 0) {

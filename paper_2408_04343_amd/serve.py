@@ -7,7 +7,11 @@ The server keeps every admitted request resident on the device as a clone of
 its template (own state, shared structure) inside one batch, and runs ticks:
 
     admit   arrived requests, first come first served, while the device
-            memory budget, the member slots and the tile capacity allow;
+            memory budget, the member slots and the tile capacity allow
+            (memory as the library reports it: every template in use is
+            charged its whole device footprint once, every request the bytes
+            snp_clone allocates for its state; tiles in the member's own
+            step-kernel tile size);
     step    the whole batch by `tick_steps` (one launch per step, each
             member stops by itself at its step limit or when it halts);
     retire  finished members: record completion latency (arrival -> the
@@ -47,17 +51,12 @@ class Request:
         return self.template.q
 
 
-def state_bytes(template: "binding.System") -> int:
-    """Device bytes of one clone of `template` (its state arrays)."""
+def clone_cost(template: "binding.System"):
+    """(device bytes, batch tiles) of one clone of `template`, from the
+    library: the bytes snp_clone allocates for a clone's state, and the
+    tiles of its step kernel."""
     info = template.info()
-    q = info["q"]
-    b = 4 * q * 3 + 2 * q * 2 + 16 * q + 256 * 8
-    if info["layout"] == binding.LAYOUT_CSR_PULL:
-        tiles = (q + 4095) // 4096
-        b += 2 * tiles * 4096 * max(1, info["emit_bits"]) // 8
-    else:
-        b += 8 * q
-    return b
+    return info["clone_bytes"], (info["q"] + info["step_tile"] - 1) // info["step_tile"]
 
 
 class Server:
@@ -72,6 +71,7 @@ class Server:
             budget_bytes = int(0.9 * free)
         self.budget = int(budget_bytes)
         self.used = 0
+        self.templates_charged = {}          # id(template) -> its device bytes, charged once
         self.tiles = 0
         self.on_done = on_done
         self.batch = binding.Batch(chunk=chunk, capacity_members=max_members,
@@ -92,11 +92,16 @@ class Server:
         self.queue.append(req)
 
     def _cost(self, req):
+        """(bytes, tiles) that admitting req takes: its clone, plus its
+        template's whole footprint if no resident request uses it yet."""
         t = req.template
         key = id(t)
         if key not in self._bytes_of:
-            self._bytes_of[key] = state_bytes(t)
-        return self._bytes_of[key], (t.q + 4095) // 4096
+            self._bytes_of[key] = clone_cost(t)
+        nbytes, ntiles = self._bytes_of[key]
+        if key not in self.templates_charged:
+            nbytes += t.info()["device_bytes"]
+        return nbytes, ntiles
 
     def _admit(self, now):
         while self.queue:
@@ -115,6 +120,13 @@ class Server:
             sysg.set_step_limit(req.steps)
             self.batch.add(sysg)
             req.admitted = now
+            key = id(req.template)
+            if key not in self.templates_charged:
+                tb = req.template.info()["device_bytes"]
+                self.templates_charged[key] = [tb, 0]
+                nbytes -= tb            # the template is charged separately
+                self.used += tb
+            self.templates_charged[key][1] += 1
             self.resident[sysg.handle.value] = (req, sysg, nbytes, ntiles)
             self.used += nbytes
             self.tiles += ntiles
@@ -136,6 +148,10 @@ class Server:
             sysg.close()
             self.used -= nbytes
             self.tiles -= ntiles
+            key = id(req.template)
+            self.templates_charged[key][1] -= 1
+            if self.templates_charged[key][1] == 0:
+                self.used -= self.templates_charged.pop(key)[0]
             self.done.append(req)
 
     # ---- driving ----------------------------------------------------------
@@ -172,15 +188,26 @@ class Server:
         elapsed = self.now()
         self.batch.sync()
         lat = np.array([r.finished - r.arrival for r in self.done]) if self.done else np.zeros(0)
+        wait = np.array([r.admitted - r.arrival for r in self.done]) if self.done else np.zeros(0)
+        serv = np.array([r.finished - r.admitted for r in self.done]) if self.done else np.zeros(0)
+        work = np.array([r.q * r.steps for r in self.done], dtype=np.float64) if self.done else np.zeros(0)
         nu = float(sum(r.q * r.steps_done for r in self.done))
+        pct = lambda a, p: float(np.percentile(a, p)) if a.size else None
+        big = work >= np.percentile(work, 90) if work.size else np.zeros(0, bool)
         return {
             "elapsed_s": elapsed, "ticks": ticks, "arrived": i, "completed": len(self.done),
             "resident_at_end": len(self.resident), "queued_at_end": len(self.queue),
             "admission_deferrals": self.deferrals,
             "completed_neuron_updates_per_s": nu / elapsed if elapsed > 0 else 0.0,
             "completed_req_per_s": len(self.done) / elapsed if elapsed > 0 else 0.0,
-            "latency_p50_s": float(np.percentile(lat, 50)) if lat.size else None,
-            "latency_p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "latency_p50_s": pct(lat, 50),
+            "latency_p99_s": pct(lat, 99),
+            # where the latency comes from: waiting for admission, or being served
+            # (sharing the batch with the others, ticks of tick_steps steps)
+            "wait_p50_s": pct(wait, 50), "wait_p99_s": pct(wait, 99),
+            "service_p50_s": pct(serv, 50), "service_p99_s": pct(serv, 99),
+            "latency_p99_s_largest_decile": pct(lat[big], 99) if big.any() else None,
+            "latency_p99_s_other_90pct": pct(lat[~big], 99) if (~big).any() else None,
         }
 
     def close(self):

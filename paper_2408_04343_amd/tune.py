@@ -73,3 +73,51 @@ def tune(spec, layout="csr_pull", steps=64, candidates=None, **kw) -> Choice:
     a.close()
     best = min(times, key=times.get)
     return Choice(layout=layout, mode=best, auto=auto, us_per_step=times, steps=steps)
+
+
+@dataclasses.dataclass
+class BatchChoice:
+    threshold: int | None     # members below it take mode_small, the others mode_large (None: all small)
+    mode_small: str
+    mode_large: str
+    ms: dict                  # threshold label -> measured milliseconds for `steps` batched steps
+    steps: int
+
+    def mode_of(self, q: int) -> str:
+        """Schedule of a member of q neurons under the chosen threshold."""
+        return self.mode_small if self.threshold is None or q < self.threshold else self.mode_large
+
+
+def threshold_label(t) -> str:
+    return "all_" + ("small" if t is None else "large") if t in (None, 0) else "q<%d" % t
+
+
+def tune_batch(systems_small, systems_large, thresholds=(0, 8192, 32768, 131072, None), steps=64, warmup=16,
+               chunk=64, mode_small="staged", mode_large="gather", capacity_tiles=0) -> BatchChoice:
+    """Measured choice of the reception schedule of each member of a batch,
+    keyed by its size.  systems_small[j] and systems_large[j] are member j
+    built in the two candidate schedules (the same system); for every
+    threshold t, the batch whose members below t neurons take the first and
+    the others the second is timed over `steps` batched steps (after
+    `warmup`), and the fastest threshold is kept.  Threshold 0 puts every
+    member in the second schedule, None every member in the first.  The
+    members' states advance during the measurement."""
+    import torch
+    ms = {}
+    for t in thresholds:
+        members = [a if (t is None or a.q < t) else b for a, b in zip(systems_small, systems_large)]
+        bt = binding.Batch(members, chunk=chunk, capacity_members=len(members), capacity_tiles=capacity_tiles)
+        try:
+            bt.step(warmup)
+            bt.sync()
+            st = bt.stream if bt.stream is not None else torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            bt.step(steps)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms[threshold_label(t)] = e0.elapsed_time(e1)
+        finally:
+            bt.close()
+    best = min(thresholds, key=lambda t: ms[threshold_label(t)])
+    return BatchChoice(threshold=best, mode_small=mode_small, mode_large=mode_large, ms=ms, steps=steps)
