@@ -317,6 +317,22 @@ int snp_expand(snp_sys* sys, int32_t nstates, const int32_t* C, const int32_t* D
                int64_t cap, int32_t* child_C, int32_t* child_D, int32_t* child_pend, int32_t* child_parent,
                int64_t* nchildren);
 
+/* snp_expand for callers that cannot allocate device memory (harnesses that
+ * forbid hipMalloc, tight exploration loops that expand level after level):
+ * same arguments, outputs, order and status codes, but every device buffer
+ * of the call (configurations, pending slots, out-lists, counts, offsets,
+ * successors) lives in one static array of the library of 32 MiB on each GPU
+ * it runs on, held until the process ends; nothing is allocated or freed.
+ * A call whose configurations, or whose successors, need more than that
+ * array (about 16 bytes per configuration cell and 16 per successor cell, q
+ * cells each, plus the system's out-lists) returns SNP_ENOTSUP with the
+ * sizes in the message.  Calls share the array: the library runs them one
+ * at a time (a process-wide lock); the array keeps the last call's contents.
+ * Synchronous on the handle's stream. */
+int snp_expand_noalloc(snp_sys* sys, int32_t nstates, const int32_t* C, const int32_t* D, const int32_t* pend,
+                       int64_t cap, int32_t* child_C, int32_t* child_D, int32_t* child_pend,
+                       int32_t* child_parent, int64_t* nchildren);
+
 /* Device copy of the representation, for inspection (host buffers):
  *   which = SNP_LAYOUT_OPTIMIZED: Sy as [z][q] int32 (-1 = null);
  *   which = SNP_LAYOUT_SLICED: the slices expanded to the same [z][q] Sy;

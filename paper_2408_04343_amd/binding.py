@@ -41,7 +41,7 @@ SYMBOLS = ["snp_opts_default", "snp_create", "snp_step", "snp_steps_done", "snp_
            "snp_strerror", "snp_last_error", "snp_set_step_limit", "snp_batch_opts_default",
            "snp_batch_create", "snp_batch_add", "snp_batch_remove", "snp_batch_step",
            "snp_batch_sync", "snp_batch_size", "snp_batch_members", "snp_batch_status",
-           "snp_batch_destroy", "snp_clone", "snp_set_synapses", "snp_expand"]
+           "snp_batch_destroy", "snp_clone", "snp_set_synapses", "snp_expand", "snp_expand_noalloc"]
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
@@ -132,6 +132,8 @@ def _load():
         "snp_clone": (ct.c_int, [vp, i32p, ct.c_uint64, vp, P(vp)]),
         "snp_set_synapses": (ct.c_int, [vp, ct.c_int64, i32p, i32p]),
         "snp_expand": (ct.c_int, [vp, ct.c_int32, i32p, i32p, i32p, ct.c_int64, i32p, i32p, i32p, i32p, i64p]),
+        "snp_expand_noalloc": (ct.c_int, [vp, ct.c_int32, i32p, i32p, i32p, ct.c_int64, i32p, i32p, i32p, i32p,
+                                          i64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -349,22 +351,23 @@ class System:
             raise ValueError("src and dst must have the same length")
         _check(lib.snp_set_synapses(self._h, len(sa), _ptr(sa), _ptr(da)))
 
-    def expand(self, C, D, pend):
+    def expand(self, C, D, pend, noalloc=False):
         """Every successor of the configurations C, D, pend ([n, q] each, or
         [q] for one) in the computation tree: dict of child C, D, pend
-        [total, q] and parent [total] (see snp_expand for the order)."""
+        [total, q] and parent [total] (see snp_expand for the order).
+        noalloc=True calls snp_expand_noalloc (no device allocation)."""
+        fn = lib.snp_expand_noalloc if noalloc else lib.snp_expand
         Ca, Da, Pa = (np.atleast_2d(_i32(x)) for x in (C, D, pend))
         if not (Ca.shape == Da.shape == Pa.shape) or Ca.shape[1] != self.q:
             raise ValueError("configurations must be [n, q] arrays of one shape")
         n = Ca.shape[0]
         total = ct.c_int64()
-        _check(lib.snp_expand(self._h, n, _ptr(Ca), _ptr(Da), _ptr(Pa), 0, None, None, None, None,
-                              ct.byref(total)))
+        _check(fn(self._h, n, _ptr(Ca), _ptr(Da), _ptr(Pa), 0, None, None, None, None, ct.byref(total)))
         t = total.value
         out = {k: np.empty((max(t, 1), self.q), np.int32) for k in ("C", "D", "pend")}
         out["parent"] = np.empty(max(t, 1), np.int32)
-        _check(lib.snp_expand(self._h, n, _ptr(Ca), _ptr(Da), _ptr(Pa), t, _ptr(out["C"]), _ptr(out["D"]),
-                              _ptr(out["pend"]), _ptr(out["parent"]), ct.byref(total)))
+        _check(fn(self._h, n, _ptr(Ca), _ptr(Da), _ptr(Pa), t, _ptr(out["C"]), _ptr(out["D"]),
+                  _ptr(out["pend"]), _ptr(out["parent"]), ct.byref(total)))
         return {k: v[:t] for k, v in out.items()}
 
     def read_layout(self, which):
