@@ -121,7 +121,7 @@ def count_bytes(binding, spec, layout, steps, warmup, info, **kw):
 
 
 def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0, cpu_seconds=0.0,
-                counters=True):
+                counters=True, threshold="tune", forced_runs=True):
     """Config 4: n independent systems (sizes log-uniform 1,000-262,144).  Every
     member is built in the two batchable pull schedules (LDS-staged and
     gathered emitted values); the tuner times the whole batch for several
@@ -147,8 +147,12 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
              for m in ("staged", "gather")}
     create_s = time.time() - t0
     cap_tiles = sum((sp.q + 1023) // 1024 for sp in specs)
-    choice = tune.tune_batch(built["staged"], built["gather"], steps=64, warmup=16, chunk=chunk,
-                             capacity_tiles=cap_tiles)
+    if threshold == "tune":
+        choice = tune.tune_batch(built["staged"], built["gather"], steps=64, warmup=16, chunk=chunk,
+                                 capacity_tiles=cap_tiles)
+    else:   # a given threshold (a profiling run times only the chosen batch)
+        choice = tune.BatchChoice(threshold=threshold, mode_small="staged", mode_large="gather", ms={},
+                                  steps=0)
     log("batch tuner: %s (ms per 64 steps: %s)" % (tune.threshold_label(choice.threshold), choice.ms))
     chosen = [a if choice.mode_of(a.q) == "staged" else b for a, b in zip(built["staged"], built["gather"])]
 
@@ -187,14 +191,14 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
     batch_ms, ntiles, dig = time_batch(chosen)
     same = dig == plain_digest
     forced = {}
-    for m in ("staged", "gather"):
+    for m in (("staged", "gather") if forced_runs else ()):
         ms, nt, d = time_batch(built[m])
         forced[m] = {"ms": ms, "neuron_updates_per_s": nu / (ms * 1e-3), "tiles": nt,
                      "equals_plain": d == plain_digest}
-    log("batched %d systems (%d neurons, tuned %s, %d tiles): %.2f ms vs plain sequential %.2f ms, digests %s; "
-        "forced staged %.2f ms, gather %.2f ms" % (n, total_q, tune.threshold_label(choice.threshold), ntiles,
-                                                  batch_ms, plain_ms, "equal" if same else "DIFFERENT",
-                                                  forced["staged"]["ms"], forced["gather"]["ms"]))
+    log("batched %d systems (%d neurons, tuned %s, %d tiles): %.2f ms vs plain sequential %.2f ms, digests %s%s" %
+        (n, total_q, tune.threshold_label(choice.threshold), ntiles, batch_ms, plain_ms,
+         "equal" if same else "DIFFERENT",
+         "".join("; forced %s %.2f ms" % (m, f["ms"]) for m, f in forced.items())))
     roof = None
     if counters:
         # exact algorithmic bytes of the batched step: every member's counters
@@ -214,8 +218,9 @@ def run_batched(binding, torch, steps=500, warmup=64, chunk=64, n=256, scale=1.0
             g.close()
         ab = float(per_step.mean())
         gbps = ab / (batch_ms / steps * 1e-3) / 1e9
+        tb, _t = measured_traffic("step_pull_batch_kernel", "csr_pull", "config4")
         roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None if tb is None else int(tb),
                 "kernel": "step_pull_batch_kernel (staged and gather launches of one step)",
                 "alg_bytes_per_launch": round(ab), "avg_launch_us": round(1e3 * batch_ms / steps, 3)}
     cpu = None
@@ -347,7 +352,7 @@ def served_check(tspecs, sampled):
         sp = tspecs[j]
         o = orc.OracleSystem(sp.q, sp.spikes0, sp.rules, sp.src, sp.dst, orc.SEM_STANDARD, sp.select, seed)
         o.step(steps)
-        ok += int(o.steps_done() == done and o.digest() == dig)
+        ok += int(o.steps_done == done and o.digest() == dig)
         o.close()
     return {"checked": len(sampled), "equal": ok}
 
@@ -373,7 +378,8 @@ def skewed_check(binding, spec, layouts, steps):
 
 
 def run_skewed(binding, torch, steps=500, warmup=16,
-               layouts=("csr_pull", "optimized", "optimized_columns", "sliced", "csr_push"), check_steps=20):
+               layouts=("csr_pull", "optimized", "optimized_columns", "sliced", "csr_push"), check_steps=20,
+               counters=True):
     """Config 3: 4,194,304 neurons, power-law out-degree (exponent 2.1, 1..4,096),
     in-degree hubs, hash choice, 500 steps.  ELL is reported analytically (its
     padded matrix, (z+1) x m pairs, exceeds the device memory)."""
@@ -404,24 +410,28 @@ def run_skewed(binding, torch, steps=500, warmup=16,
             out["layouts"][lay] = {"error": str(e)}
             log("config3 %s: %s" % (lay, e))
             continue
-        a, pk, _cnt = count_bytes(binding, spec, lay, min(steps, 200), warmup, r["info"])
-        r["alg_bytes_per_step"] = a
-        r["packed_bytes_per_step"] = pk
-        r["alg_GBps"] = a / (r["ms_per_step"] * 1e-3) / 1e9
-        r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
         r["neuron_updates_per_s"] = spec.q / (r["ms_per_step"] * 1e-3)
+        if counters:
+            a, pk, _cnt = count_bytes(binding, spec, lay, min(steps, 200), warmup, r["info"])
+            r["alg_bytes_per_step"] = a
+            r["packed_bytes_per_step"] = pk
+            r["alg_GBps"] = a / (r["ms_per_step"] * 1e-3) / 1e9
+            r["frac_of_peak"] = r["alg_GBps"] / HBM_PEAK_GBS
         r["kernel"] = step_kernel(lay, r["info"])
         out["layouts"][lay] = {k: v for k, v in r.items() if k != "info"}
-        log("config3 %-10s %.4f ms/step  %.3e nu/s  %.0f GB/s alg (%.3f of peak)" %
-            (lay, r["ms_per_step"], r["neuron_updates_per_s"], r["alg_GBps"], r["frac_of_peak"]))
+        log("config3 %-10s %.4f ms/step  %.3e nu/s  %s" %
+            (lay, r["ms_per_step"], r["neuron_updates_per_s"],
+             "%.0f GB/s alg (%.3f of peak)" % (r["alg_GBps"], r["frac_of_peak"]) if counters else ""))
     ok = {k: v for k, v in out["layouts"].items() if "frac_of_peak" in v}
     for tag, keys in (("roofline_pull", [k for k in ok if k == "csr_pull"]),
                       ("roofline_push", [k for k in ok if k != "csr_pull"])):
         if keys:
             best = min(keys, key=lambda k: ok[k]["ms_per_step"])
             v = ok[best]
+            tb, _t = measured_traffic(v["kernel"], best, "config3")
             out[tag] = {"bound": "hbm", "achieved": round(v["alg_GBps"], 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(v["frac_of_peak"], 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(v["frac_of_peak"], 4),
+                        "traffic": None if tb is None else int(tb),
                         "kernel": v["kernel"], "layout": best, "alg_bytes_per_launch": round(v["alg_bytes_per_step"]),
                         "avg_launch_us": round(v["ms_per_step"] * 1e3, 3)}
     if check_steps > 0:
@@ -594,8 +604,14 @@ def call_latency(binding, torch, spec, layout, calls=200, warmup=16, **kw):
 _COMMON = ["paper_2408_04343_amd/csrc/snp_device.h", "paper_2408_04343_amd/csrc/snp_internal.h"]
 KERNEL_SOURCES = {
     "step_pull_kernel": ["paper_2408_04343_amd/csrc/snp_step_pull.h",
-                         "paper_2408_04343_amd/csrc/snp_step_pull.hip"] + _COMMON,
-    "step_bin_kernel": ["paper_2408_04343_amd/csrc/snp_step_bin.hip"] + _COMMON,
+                         "paper_2408_04343_amd/csrc/snp_step_pull.hip",
+                         "paper_2408_04343_amd/csrc/snp_step_pull_gather.hip"] + _COMMON,
+    "step_pull_batch_kernel": ["paper_2408_04343_amd/csrc/snp_step_pull.h",
+                               "paper_2408_04343_amd/csrc/snp_step_pull.hip",
+                               "paper_2408_04343_amd/csrc/snp_step_pull_gather.hip"] + _COMMON,
+    "step_bin_kernel": ["paper_2408_04343_amd/csrc/snp_step_bin.h", "paper_2408_04343_amd/csrc/snp_step_bin.hip",
+                        "paper_2408_04343_amd/csrc/snp_step_bin_csr.hip",
+                        "paper_2408_04343_amd/csrc/snp_step_bin_sy.hip"] + _COMMON,
     "step_push_kernel": ["paper_2408_04343_amd/csrc/snp_step_push.hip"] + _COMMON,
 }
 
@@ -616,15 +632,15 @@ def kernel_source_hash(kernel="step_pull_kernel"):
     return h.hexdigest()[:16]
 
 
-def traffic_path(kernel, layout):
-    return os.path.join(ROOT, "profiles", "traffic_%s_%s_config2.json" % (kernel, layout))
+def traffic_path(kernel, layout, workload="config2"):
+    return os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (kernel, layout, workload))
 
 
-def measured_traffic(kernel="step_pull_kernel", layout="csr_pull"):
-    """HBM bytes per launch of a step kernel on config 2 from the committed
+def measured_traffic(kernel="step_pull_kernel", layout="csr_pull", workload="config2"):
+    """HBM bytes per launch of a step kernel on a workload from the committed
     rocprofv3 counter summary, if it was taken on the current kernel sources."""
     try:
-        with open(traffic_path(kernel, layout)) as fh:
+        with open(traffic_path(kernel, layout, workload)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None, None
@@ -663,7 +679,7 @@ def _pmc_per_kernel(csv_path, counter):
     return out
 
 
-def write_traffic(run_dir, copy_dir, kernel, layout, skip=8):
+def write_traffic(run_dir, copy_dir, kernel, layout, skip=8, workload="config2"):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of this
     bench (FETCH_SIZE in run_dir/fetch, WRITE_SIZE in run_dir/write) and of
     the copy probe of 512 MiB (same layout under copy_dir), each counter scaled by what
@@ -673,23 +689,25 @@ def write_traffic(run_dir, copy_dir, kernel, layout, skip=8):
     w = _pmc_per_kernel(os.path.join(run_dir, "write", "run_counter_collection.csv"), "WRITE_SIZE")
     cf = _pmc_per_kernel(os.path.join(copy_dir, "fetch", "run_counter_collection.csv"), "FETCH_SIZE")
     cw = _pmc_per_kernel(os.path.join(copy_dir, "write", "run_counter_collection.csv"), "WRITE_SIZE")
-    kf = [v for k, v in f.items() if kernel in k]
-    kw = [v for k, v in w.items() if kernel in k]
+    kf = [v for k, v in f.items() if kernel + "<" in k]
+    kw = [v for k, v in w.items() if kernel + "<" in k]
     copy_f = [v for k, v in cf.items() if "copyBuffer" in k][0]
     copy_w = [v for k, v in cw.items() if "copyBuffer" in k][0]
     copy_bytes = 512 * (1 << 20)
     fetch_scale = copy_bytes / (float(np.median(copy_f)) * 1024)
     write_scale = copy_bytes / (float(np.median(copy_w)) * 1024)
-    fk = np.array(kf[0][skip:]) * 1024 * fetch_scale
-    wk = np.array(kw[0][skip:]) * 1024 * write_scale
-    t = {"kernel": kernel, "layout": layout, "workload": "config2", "source_hash": kernel_source_hash(kernel),
-         "launches": int(fk.size), "fetch_kib_raw_mean": float(np.mean(kf[0][skip:])),
-         "write_kib_raw_mean": float(np.mean(kw[0][skip:])),
+    # one instantiation per reception mode may run at each step (a batch of
+    # staged and gathered members): a step's traffic is the sum of their means
+    rf = sum(float(np.mean(v[skip:])) for v in kf)
+    rw = sum(float(np.mean(v[skip:])) for v in kw)
+    t = {"kernel": kernel, "layout": layout, "workload": workload, "source_hash": kernel_source_hash(kernel),
+         "instantiations": len(kf), "launches": int(sum(len(v[skip:]) for v in kf)),
+         "fetch_kib_raw_mean": rf, "write_kib_raw_mean": rw,
          "copy_fetch_kib_raw": float(np.median(copy_f)), "copy_write_kib_raw": float(np.median(copy_w)),
          "fetch_scale": fetch_scale, "write_scale": write_scale,
-         "read_bytes_per_launch": float(np.mean(fk)), "write_bytes_per_launch": float(np.mean(wk)),
-         "traffic_bytes_per_launch": float(np.mean(fk) + np.mean(wk))}
-    with open(traffic_path(kernel, layout), "w") as fh:
+         "read_bytes_per_launch": rf * 1024 * fetch_scale, "write_bytes_per_launch": rw * 1024 * write_scale,
+         "traffic_bytes_per_launch": rf * 1024 * fetch_scale + rw * 1024 * write_scale}
+    with open(traffic_path(kernel, layout, workload), "w") as fh:
         json.dump(t, fh, indent=1)
     print(json.dumps(t))
 
@@ -735,11 +753,20 @@ def main():
     ap.add_argument("--skewed-check-steps", type=int, default=20,
                     help="config-3 steps whose digests are compared with the oracle's")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
-    ap.add_argument("--write-traffic", nargs=4, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "LAYOUT"),
+    ap.add_argument("--write-traffic", nargs=5, metavar=("RUN_DIR", "COPY_DIR", "KERNEL", "LAYOUT", "WORKLOAD"),
                     help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into the traffic file of a layout")
+    ap.add_argument("--skip-config2", action="store_true",
+                    help="run only the other workloads (batched, skewed, sorting, ratios, served)")
+    ap.add_argument("--skewed-layouts", default="csr_pull,optimized,optimized_columns,sliced,csr_push")
+    ap.add_argument("--skewed-steps", type=int, default=500)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--batch-threshold", default="tune",
+                    help="'tune', or members below this many neurons staged (profiling runs)")
+    ap.add_argument("--no-batch-forced", action="store_true", help="skip the forced all-staged/gathered batches")
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(*args.write_traffic)
+        rd, cd, kern, lay, wk = args.write_traffic
+        write_traffic(rd, cd, kern, lay, workload=wk)
         return
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
@@ -802,15 +829,18 @@ def main():
                 "packed_frac": round(r["packed_frac_of_peak"], 4),
                 "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(r["alg_frac_of_copy"], 4)}
 
+    if args.skip_config2:
+        layouts = []
     results = {lay: measure(spec, lay) for lay in layouts}
     # the same system with the hash choice (configs 3-5 use it)
     spec_h = dataclasses.replace(spec, select=wl.SELECT_HASH, name="config2-large-hash")
     results_hash = {lay: measure(spec_h, lay) for lay in [args.layout, "ell"] if lay in layouts}
-    head = results[args.layout]
-    value = spec.q * args.steps / (head["total_ms"] * 1e-3)
+    head = results.get(args.layout, {"ms_per_step": None, "total_ms": None, "info": {}, "step_ms_p50": None,
+                                     "step_ms_p99": None})
+    value = spec.q * args.steps / (head["total_ms"] * 1e-3) if head["total_ms"] else None
     # per-call latency of single steps: config 1 (launch-bound) and config 2
     latency = {}
-    if not args.no_latency:
+    if not args.no_latency and not args.skip_config2:
         c1 = wl.config1()
         for name, sp, lays in (("config1", c1, ("csr_pull", "ell")), ("config2", spec, (args.layout, "ell"))):
             for lay in dict.fromkeys(lays):
@@ -818,9 +848,14 @@ def main():
                 log("latency %s %s: %s" % (name, lay, latency["%s_%s" % (name, lay)]))
     batched = None
     if not args.no_batch:
-        batched = run_batched(binding, torch, scale=args.batch_scale,
-                              cpu_seconds=0.0 if args.no_cpu else args.cpu_seconds / 2)
-    skewed = None if args.no_skewed else run_skewed(binding, torch, check_steps=args.skewed_check_steps)
+        thr = args.batch_threshold if args.batch_threshold == "tune" else (
+            None if args.batch_threshold == "none" else int(args.batch_threshold))
+        batched = run_batched(binding, torch, steps=args.batch_steps, scale=args.batch_scale,
+                              cpu_seconds=0.0 if args.no_cpu else args.cpu_seconds / 2,
+                              counters=not args.no_counters, threshold=thr, forced_runs=not args.no_batch_forced)
+    skewed = None if args.no_skewed else run_skewed(
+        binding, torch, steps=args.skewed_steps, check_steps=args.skewed_check_steps,
+        layouts=tuple(x for x in args.skewed_layouts.split(",") if x), counters=not args.no_counters)
     sort_sizes = [int(x) for x in args.sort_n.split(",") if x]
     sorting = run_sort(binding, torch, sort_sizes) if sort_sizes else None
     ratios = None if args.ratio_n <= 0 else run_ratios(binding, torch, args.ratio_n)
@@ -829,7 +864,7 @@ def main():
         cap = batched["batched"]["neuron_updates_per_s"] if batched else value
         served = run_served(binding, torch, args.serve_rate, args.serve_seconds, capacity_nu=cap)
     cpu = cpu_par = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.skip_config2:
         log("cpu baseline (oracle) for ~%.0f s single-threaded, ~%.0f s OpenMP ..." %
             (args.cpu_seconds, args.cpu_seconds))
         cpu = cpu_baseline(spec, args.cpu_seconds)
@@ -847,7 +882,7 @@ def main():
                    "select": "first", "semantics": "standard", "graph_chunk": args.chunk,
                    "pull_tile_log2": head["info"].get("pull_tile_log2"),
                    "rule_bytes": head["info"].get("rule_bytes")},
-        "roofline": roof(head),
+        "roofline": roof(head) if results else None,
         "roofline_ell": roof(results["ell"]) if "ell" in results else None,
         "cpu_baseline": cpu_par if cpu_par is not None else cpu,
         "cpu_baseline_single_thread": cpu,
@@ -859,7 +894,8 @@ def main():
         "sorting_family": sorting,
         "layout_ratios": ratios,
         "latency_ms_per_step_chunks": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"],
-                                       "over": "graph chunks of %d steps (mean per step)" % args.chunk},
+                                       "over": "graph chunks of %d steps (mean per step)" % args.chunk}
+                                      if results else None,
         "layouts": rl(results),
     }
     print(json.dumps(out), flush=True)

@@ -32,10 +32,10 @@ constexpr int32_t BIN_WL = 3 * 64;      // LDS words of one wave's list of rows
 // (even) long-row list [BIN_HMAX][4] | row lists [BIN_WAVES][BIN_WL] | from
 // bin_union_word on, the reception and selection arrays, later the stage
 // of outgoing records (bin_stage_chunks 16-byte chunks).
-__host__ __device__ inline int32_t bin_union_word(int32_t nb) {
+__host__ __device__ constexpr int32_t bin_union_word(int32_t nb) {
   return ((((3 * nb + 1) & ~1) + 4 * BIN_HMAX + BIN_WAVES * BIN_WL) + 3) & ~3;
 }
-__host__ __device__ inline int32_t bin_stage_chunks(int32_t nb) {
+__host__ __device__ constexpr int32_t bin_stage_chunks(int32_t nb) {
   return (BIN_LDS_BYTES / 4 - bin_union_word(nb)) / 4;
 }
 constexpr int32_t PUSH_LIGHT = 32;      // wide push: row entries a thread walks alone

@@ -34,6 +34,12 @@ constexpr int BIN_ROWS = 8;                     // strided rows: entries loaded 
 constexpr int BIN_WAVE_PIECES = 64;             // contiguous rows: 16-byte pieces a wave walks alone
 constexpr int BIN_U = 4;                        // pieces (chunks) in flight per thread
 static_assert(BIN_NT / 64 == BIN_WAVES, "one row list per wave");
+constexpr int BIN_RPT = (BIN_MAX_TILES + BIN_NT - 1) / BIN_NT;  // regions per thread in the reception
+// the reception arrays (acc, pos, roff, rcnt, defer) fit beside the lists
+// and leave every region of the largest system its count chunk in the stage
+static_assert(bin_union_word(BIN_MAX_TILES) + BIN_TILE + 3 * BIN_MAX_TILES + 1 + BIN_TILE / 2 <= BIN_LDS_BYTES / 4,
+              "binned LDS too small for the reception arrays");
+static_assert(bin_stage_chunks(BIN_MAX_TILES) >= BIN_MAX_TILES, "binned stage too small");
 
 // Exclusive prefix sum of v over the block; *total = the sum of all v.
 template <int NT>
@@ -147,11 +153,11 @@ __device__ __forceinline__ void bin_receive(const SysDev& s, int32_t tile, int32
   const int32_t R = bin_r(s), H = bin_h(s);
   const uint4* bp = pick(s.bins[0], s.bins[1], rbuf);
   const int32_t* op = s.boff + (size_t)tile * (nb + 1);
-  uint4 h[2];
-  int32_t cnt[2], rest[2];
+  uint4 h[BIN_RPT];
+  int32_t cnt[BIN_RPT], rest[BIN_RPT];
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int32_t b = 2 * tid + x;
+  for (int x = 0; x < BIN_RPT; ++x) {
+    const int32_t b = BIN_RPT * tid + x;
     h[x] = make_uint4(0, 0, 0, 0);
     cnt[x] = 0;
     rest[x] = 0;
@@ -163,22 +169,28 @@ __device__ __forceinline__ void bin_receive(const SysDev& s, int32_t tile, int32
       }
     }
   }
+  int32_t mine = 0;
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int32_t b = 2 * tid + x;
+  for (int x = 0; x < BIN_RPT; ++x) {
+    const int32_t b = BIN_RPT * tid + x;
     if (b < nb) {
       cnt[x] = (int32_t)h[x].x;
       rest[x] = (cnt[x] + H + R - 1) / R - 1;
       L.rcnt[b] = cnt[x];
+      mine += rest[x];
     }
   }
   int32_t total;
-  const int32_t ex = block_exscan<BIN_NT>(rest[0] + rest[1], wsum, &total);
-  if (2 * tid < nb) L.pos[2 * tid] = ex;
-  if (2 * tid + 1 < nb) L.pos[2 * tid + 1] = ex + rest[0];
+  int32_t ex = block_exscan<BIN_NT>(mine, wsum, &total);
+#pragma unroll
+  for (int x = 0; x < BIN_RPT; ++x) {
+    const int32_t b = BIN_RPT * tid + x;
+    if (b < nb) L.pos[b] = ex;
+    ex += rest[x];
+  }
   if (tid == 0) L.pos[nb] = total;
 #pragma unroll
-  for (int x = 0; x < 2; ++x) add_chunk(L.acc, h[x], H, min(R, cnt[x] + H), b2);
+  for (int x = 0; x < BIN_RPT; ++x) add_chunk(L.acc, h[x], H, min(R, cnt[x] + H), b2);
   __syncthreads();
   for (int32_t e0 = tid; e0 < total; e0 += BIN_U * BIN_NT) {
     uint4 rv[BIN_U];
