@@ -243,6 +243,51 @@ __device__ __forceinline__ void bin_put(const SysDev& s, const BinLds& L, uint4*
   }
 }
 
+// Records t[r], v[r] of one lane for the set bits r of okm: every slot is
+// taken before any record is written, so that the lane's returning LDS
+// atomics are in flight together; the record width and the spill test are
+// uniform branches around the writes.
+template <int NR>
+__device__ __forceinline__ void bin_put_n(const SysDev& s, const BinLds& L, uint4* gb, const int32_t* t,
+                                          const int32_t* v, uint32_t okm) {
+  int32_t slot[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    slot[r] = 0;
+    if ((okm >> r) & 1u) slot[r] = atomicAdd(&L.lcnt[t[r] >> BIN_TB], 1);
+  }
+  if (s.bfull) {
+    if (s.brec == 2) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if ((okm >> r) & 1u)
+          ((uint16_t*)L.stage)[slot[r]] = (uint16_t)((uint32_t)(t[r] & (BIN_TILE - 1)) | ((uint32_t)v[r] << BIN_TB));
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if ((okm >> r) & 1u)
+          ((uint32_t*)L.stage)[slot[r]] = (uint32_t)(t[r] & (BIN_TILE - 1)) | ((uint32_t)v[r] << BIN_TB);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (!((okm >> r) & 1u)) continue;
+      const int32_t tt = t[r] >> BIN_TB;
+      const uint32_t rec = (uint32_t)(t[r] & (BIN_TILE - 1)) | ((uint32_t)v[r] << BIN_TB);
+      const uint32_t sg = L.stg[tt];
+      const int32_t R = s.brec == 2 ? 8 : 4;
+      if (slot[r] < (int32_t)(((sg & 0xFFFFu) + (sg >> 16)) * (uint32_t)R)) {
+        if (R == 8) ((uint16_t*)L.stage)[slot[r]] = (uint16_t)rec;
+        else ((uint32_t*)L.stage)[slot[r]] = rec;
+      } else {
+        const int32_t j = slot[r] - (int32_t)(sg & 0xFFFFu) * R;
+        if (R == 8) ((uint16_t*)(gb + L.offp[tt]))[j] = (uint16_t)rec;
+        else ((uint32_t*)(gb + L.offp[tt]))[j] = rec;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ contiguous rows --
 //
 // A row is entries [E0, E0 + N) of the layout's array read as 16-byte
@@ -309,6 +354,42 @@ __device__ __forceinline__ void put_piece(const SysDev& s, const BinLds& L, uint
   }
 }
 
+// Entries per 16-byte piece of a contiguous row, and pieces whose entries
+// one lane puts together.
+template <int LAYOUT>
+constexpr int kEpp = LAYOUT == L_ELL ? 2 : 4;
+template <int LAYOUT>
+constexpr int kGroup = 8 / kEpp<LAYOUT>;
+
+// The entries lo .. hi-1 of piece x as records at t[base ..], v[base ..],
+// bits of okm (value v unless the layout stores values).
+template <int LAYOUT>
+__device__ __forceinline__ void collect_piece(const int4& x, int32_t lo, int32_t hi, int32_t v, int64_t col0,
+                                              int32_t* t, int32_t* w, uint32_t& okm, int base) {
+  if (LAYOUT == L_ELL) {
+    t[base] = x.x;
+    w[base] = x.y;
+    t[base + 1] = x.z;
+    w[base + 1] = x.w;
+    okm |= (uint32_t)(lo <= 0 && hi > 0 && x.x >= 0) << base;
+    okm |= (uint32_t)(lo <= 1 && hi > 1 && x.z >= 0) << (base + 1);
+  } else {
+    const int32_t e[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (LAYOUT == L_SPARSE) {
+        t[base + c] = (int32_t)(col0 + c);
+        w[base + c] = e[c];
+        okm |= (uint32_t)(c >= lo && c < hi && e[c] != 0) << (base + c);
+      } else {
+        t[base + c] = e[c];
+        w[base + c] = v;
+        okm |= (uint32_t)(c >= lo && c < hi && e[c] >= 0) << (base + c);
+      }
+    }
+  }
+}
+
 // Loads piece f of a list of rows (keys kk, entries | value << 12 or
 // entries and values, inclusive piece counts inc, n entries) and returns
 // what put_piece needs.
@@ -370,7 +451,15 @@ __device__ __forceinline__ void wave_walk(const SysDev& s, const BinLds& L, uint
       }
     }
 #pragma unroll
-    for (int u = 0; u < BIN_U; ++u) put_piece<LAYOUT>(s, L, gb, pc[u].x, pc[u].lo, pc[u].hi, pc[u].v, pc[u].col0);
+    for (int g = 0; g < BIN_U; g += kGroup<LAYOUT>) {
+      int32_t t[8], w[8];
+      uint32_t okm = 0;
+#pragma unroll
+      for (int u = 0; u < kGroup<LAYOUT>; ++u)
+        collect_piece<LAYOUT>(pc[g + u].x, pc[g + u].lo, pc[g + u].hi, pc[g + u].v, pc[g + u].col0, t, w, okm,
+                              u * kEpp<LAYOUT>);
+      bin_put_n<8>(s, L, gb, t, w, okm);
+    }
   }
   wave_lds_sync();  // the list is rewritten for the next rows
 }
@@ -673,11 +762,16 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
 #pragma unroll
       for (int r = 0; r < BIN_NPT; ++r) {
         bool open = true;
+        int32_t t[BIN_ROWS], w[BIN_ROWS];
+        uint32_t okm = 0;
 #pragma unroll
         for (int u = 0; u < BIN_ROWS; ++u) {
           open = open && x[r][u].x >= 0;
-          if (open) bin_put(s, L, gb, x[r][u].x, x[r][u].y);
+          t[u] = x[r][u].x;
+          w[u] = x[r][u].y;
+          okm |= (uint32_t)open << u;
         }
+        bin_put_n<BIN_ROWS>(s, L, gb, t, w, okm);
         more[r] = open && jend[r] > BIN_ROWS;
       }
     }
@@ -695,11 +789,16 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
       for (int32_t jb = BIN_ROWS; jb < jend[r] && open; jb += BIN_ROWS) {
         int2 x[BIN_ROWS];
         bin_load<LAYOUT>(s, i, rule[r], o[r].emit, e0[r], jb, jend[r], x);
+        int32_t t[BIN_ROWS], w[BIN_ROWS];
+        uint32_t okm = 0;
 #pragma unroll
         for (int u = 0; u < BIN_ROWS; ++u) {
           open = open && x[u].x >= 0;
-          if (open) bin_put(s, L, gb, x[u].x, x[u].y);
+          t[u] = x[u].x;
+          w[u] = x[u].y;
+          okm |= (uint32_t)open << u;
         }
+        bin_put_n<BIN_ROWS>(s, L, gb, t, w, okm);
       }
     }
   }
