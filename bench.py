@@ -842,7 +842,8 @@ def main():
     latency = {}
     if not args.no_latency and not args.skip_config2:
         c1 = wl.config1()
-        for name, sp, lays in (("config1", c1, ("csr_pull", "ell")), ("config2", spec, (args.layout, "ell"))):
+        for name, sp, lays in (("config1", c1, ("csr_pull", "ell", "optimized")),
+                               ("config2", spec, (args.layout, "ell"))):
             for lay in dict.fromkeys(lays):
                 latency["%s_%s" % (name, lay)] = call_latency(binding, torch, sp, lay, calls=args.latency_calls)
                 log("latency %s %s: %s" % (name, lay, latency["%s_%s" % (name, lay)]))
