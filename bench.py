@@ -61,10 +61,10 @@ def packed_bytes(layout, q, c, rule_bytes, emit_w):
     if base == "csr_pull":
         return state + 4 * q + 4 * c["recv_in_edges"] + 2 * (emit_w * q // 8)
     push = 8 * q + 4 * G
-    if base in ("optimized", "optimized_columns", "sliced"):
+    # ELL: the neurons of the pairs only (past row 0 a column's values are its
+    # rule's p, taken from the rule record)
+    if base in ("optimized", "optimized_columns", "sliced", "ell"):
         return state + push + 4 * (G + E)
-    if base == "ell":
-        return state + push + 8 * (G + E)
     return state + push + 4 * G + 8 * E
 
 

@@ -838,13 +838,17 @@ int snp_create(int32_t q, const int32_t* spikes0, int32_t m, const snp_rule* rul
       d.sy = sy;
       if (hipSuccess != launch_build_sy(d, sy, s->stream)) return bail(fail(SNP_EDEVICE, "build_sy"));
     } else if (o.layout == SNP_LAYOUT_ELL) {
-      // rule by rule, every column padded to an even number of pairs with nulls
+      // rule by rule, every column padded to an even number of pairs with
+      // nulls; the neurons of all pairs, then their values (the step reads
+      // the neurons only: past row 0 a column's values are its rule's p)
       const size_t rows = d.ell_rows ? (size_t)(z + 1) : (size_t)((z + 2) & ~1);
-      int2* ell = nullptr;
-      if ((st = alloc_fill(s, (void**)&ell, 8 * rows * (size_t)std::max(m, 1), 0xFF)) != SNP_OK)
+      const size_t ent = rows * (size_t)std::max(m, 1);
+      int32_t* ell = nullptr;
+      if ((st = alloc_fill(s, (void**)&ell, 8 * ent, 0xFF)) != SNP_OK)
         return bail(st == SNP_ENOMEM ? fail(SNP_ENOMEM, "ELL does not fit in device memory") : st);
-      d.ell = ell;
-      if (hipSuccess != launch_build_ell(d, ell, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
+      d.ell_t = ell;
+      d.ell_v = ell + ent;
+      if (hipSuccess != launch_build_ell(d, ell, ell + ent, s->stream)) return bail(fail(SNP_EDEVICE, "build_ell"));
     }
   }
   const int64_t structure_bytes = s->device_bytes;
@@ -1166,16 +1170,16 @@ int snp_read_layout(snp_sys* s, int32_t which, int32_t* out, int64_t count, int6
         out[r * q + i] = r < h ? tmp[(size_t)(off[(size_t)b] + r * SLICE + i % SLICE)] : -1;
     }
   } else if (which == SNP_LAYOUT_ELL) {
-    if (!s->d.ell) return fail(SNP_EINVAL, "handle does not use the ELL layout");
-    const size_t dev = 2 * (size_t)(s->d.ell_rows ? z + 1 : (z + 2) & ~1) * (size_t)std::max(m, 1);
-    std::vector<int32_t> tmp(dev);
-    HIPCHK(hipMemcpy(tmp.data(), s->d.ell, 4 * dev, hipMemcpyDeviceToHost));
+    if (!s->d.ell_t) return fail(SNP_EINVAL, "handle does not use the ELL layout");
+    const size_t ent = (size_t)(s->d.ell_rows ? z + 1 : (z + 2) & ~1) * (size_t)std::max(m, 1);
+    std::vector<int32_t> tmp(2 * ent);
+    HIPCHK(hipMemcpy(tmp.data(), s->d.ell_t, 8 * ent, hipMemcpyDeviceToHost));
     for (int64_t row = 0; row <= z; ++row)
       for (int32_t sl = 0; sl < m; ++sl) {
-        const int64_t src = ell_index(s->d, sl, (int32_t)row) * 2;
+        const int64_t src = ell_index(s->d, sl, (int32_t)row);
         const int64_t dst = (row * m + (s->base ? s->base : s)->h_rid[sl]) * 2;
         out[dst] = tmp[(size_t)src];
-        out[dst + 1] = tmp[(size_t)src + 1];
+        out[dst + 1] = tmp[ent + (size_t)src];
       }
   } else if (which == SNP_LAYOUT_CSR_PUSH) {
     if (!s->d.out_ptr) return fail(SNP_EINVAL, "handle keeps no out-neighbour lists");

@@ -103,7 +103,8 @@ struct SysDev {
   const int32_t* dense;      // SPARSE: [m][q] spikes rule slot r sends to neuron t
   const int64_t* sy_off;     // SLICED: [q/64 + 1] first entry of each slice; slice b is
                              //   [h_b][64] row-major, h_b = (sy_off[b+1] - sy_off[b]) / 64
-  const int2* ell;           // ELL: (neuron, value) pairs, (-1, 0) = null; [m][z+1] (a rule's
+  const int32_t* ell_t;      // ELL: the pairs (neuron, value) as two planes of one buffer, the
+  const int32_t* ell_v;      //   neurons (-1 = null) and the values, each [m][z+1] (a rule's
                              //   column contiguous) or, with ell_rows, [z+1][m]
   int32_t ell_rows;
   int32_t sy_rows;           // OPTIMIZED: 1 = [z][q], 0 = [q][z4] (columns of z rounded up to 4)
@@ -160,6 +161,11 @@ __host__ __device__ inline int64_t ell_index(const SysDev& s, int32_t slot, int3
   return s.ell_rows ? (int64_t)row * s.m + slot : (int64_t)slot * ((s.z + 2) & ~1) + row;
 }
 
+// Pair (neuron, value) at ELL entry idx.
+__host__ __device__ inline int2 ell_pair(const SysDev& s, int64_t idx) {
+  return make_int2(s.ell_t[idx], s.ell_v[idx]);
+}
+
 // Entry (neuron i, row) of the global Sy.
 __host__ __device__ inline int64_t sy_index(const SysDev& s, int32_t i, int32_t row) {
   return s.sy_rows ? (int64_t)row * s.q + i : (int64_t)i * ((s.z + 3) & ~3) + row;
@@ -208,7 +214,7 @@ hipError_t launch_digest(const int32_t* C, const int32_t* D, const int32_t* S, i
 hipError_t launch_build_sy(const SysDev& s, int32_t* sy, hipStream_t st);
 hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st);
 hipError_t launch_build_dense(const SysDev& s, int32_t* dense, hipStream_t st);
-hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st);
+hipError_t launch_build_ell(const SysDev& s, int32_t* ell_t, int32_t* ell_v, hipStream_t st);
 hipError_t launch_restore(const SysDev& s, int32_t sbuf, const int32_t* C, const int32_t* D,
                           const int32_t* P, const int32_t* S, const int32_t* slot_of_rule,
                           hipStream_t st);

@@ -283,24 +283,27 @@ hipError_t launch_build_sy_sliced(const SysDev& s, int32_t* sy, hipStream_t st) 
 // 1..deg = (target, +p) for p > 0, the rest (-1, 0); stored column by column
 // ([m][z+1]) or row by row ([z+1][m]), see ell_index.
 template <int RB>
-__global__ void build_ell_kernel(SysDev s, int2* ell) {
+__global__ void build_ell_kernel(SysDev s, int32_t* ell_t, int32_t* ell_v) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.q) return;
   const int32_t e0 = s.out_ptr[i], deg = s.out_ptr[i + 1] - e0;
   for (int32_t r = s.rs[i]; r < s.rs[i + 1]; ++r) {
     const Rule rr = load_rule<RB>(s, r);
-    ell[ell_index(s, r, 0)] = make_int2(i, -rr.c);
+    ell_t[ell_index(s, r, 0)] = i;
+    ell_v[ell_index(s, r, 0)] = -rr.c;
     for (int32_t row = 1; row <= s.z; ++row) {
       const bool on = rr.p > 0 && row <= deg;
-      ell[ell_index(s, r, row)] = on ? make_int2(s.out_col[e0 + row - 1], rr.p) : make_int2(-1, 0);
+      ell_t[ell_index(s, r, row)] = on ? s.out_col[e0 + row - 1] : -1;
+      ell_v[ell_index(s, r, row)] = on ? rr.p : 0;
     }
   }
 }
 
-hipError_t launch_build_ell(const SysDev& s, int2* ell, hipStream_t st) {
-  if (s.rule_bytes == 4) build_ell_kernel<4><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
-  else if (s.rule_bytes == 8) build_ell_kernel<8><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
-  else build_ell_kernel<16><<<(s.q + 255) / 256, 256, 0, st>>>(s, ell);
+hipError_t launch_build_ell(const SysDev& s, int32_t* ell_t, int32_t* ell_v, hipStream_t st) {
+  const int g = (s.q + 255) / 256;
+  if (s.rule_bytes == 4) build_ell_kernel<4><<<g, 256, 0, st>>>(s, ell_t, ell_v);
+  else if (s.rule_bytes == 8) build_ell_kernel<8><<<g, 256, 0, st>>>(s, ell_t, ell_v);
+  else build_ell_kernel<16><<<g, 256, 0, st>>>(s, ell_t, ell_v);
   return hipGetLastError();
 }
 

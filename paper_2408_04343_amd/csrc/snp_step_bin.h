@@ -291,11 +291,12 @@ __device__ __forceinline__ void bin_put_n(const SysDev& s, const BinLds& L, uint
 // ------------------------------------------------------ contiguous rows --
 //
 // A row is entries [E0, E0 + N) of the layout's array read as 16-byte
-// pieces of 2^lg entries: ELL stored rule by rule (pairs (target, value),
-// lg 1, E0 = the rule's column + 1: row 0 holds the consumption, applied by
-// the owner), CSR (targets, lg 2, E0 = the row start), Sy stored neuron by
-// neuron (targets, lg 2, E0 = the neuron's column) and the dense matrix of
-// the Sparse layout (values, lg 2, E0 = the rule's row; target = column).
+// pieces of 4 entries: ELL stored rule by rule (the neurons of the pairs,
+// E0 = the rule's column + 1: row 0 holds the consumption, applied by the
+// owner; the value of every other pair is the rule's p, the row's value),
+// CSR (targets, E0 = the row start), Sy stored neuron by neuron (targets,
+// E0 = the neuron's column) and the dense matrix of the Sparse layout
+// (values, E0 = the rule's row; target = column).
 
 template <int LAYOUT>
 constexpr bool kCanContig = LAYOUT != L_SLICED;
@@ -309,11 +310,11 @@ __device__ __forceinline__ bool bin_contiguous(const SysDev& s) {
 }
 
 template <int LAYOUT>
-constexpr int kLg = LAYOUT == L_ELL ? 1 : 2;
+constexpr int kLg = 2;
 
 template <int LAYOUT>
 __device__ __forceinline__ const int4* row_base(const SysDev& s) {
-  if (LAYOUT == L_ELL) return reinterpret_cast<const int4*>(s.ell);
+  if (LAYOUT == L_ELL) return reinterpret_cast<const int4*>(s.ell_t);
   if (LAYOUT == L_OPT) return reinterpret_cast<const int4*>(s.sy);
   if (LAYOUT == L_SPARSE) return reinterpret_cast<const int4*>(s.dense);
   return reinterpret_cast<const int4*>(s.out_col);
@@ -338,10 +339,7 @@ __device__ __forceinline__ int32_t row_pieces(int64_t e0, int32_t n, int lg) {
 template <int LAYOUT>
 __device__ __forceinline__ void put_piece(const SysDev& s, const BinLds& L, uint4* gb, const int4& x,
                                           int32_t lo, int32_t hi, int32_t v, int64_t col0) {
-  if (LAYOUT == L_ELL) {
-    if (lo <= 0 && hi > 0 && x.x >= 0) bin_put(s, L, gb, x.x, x.y);
-    if (lo <= 1 && hi > 1 && x.z >= 0) bin_put(s, L, gb, x.z, x.w);
-  } else if (LAYOUT == L_SPARSE) {
+  if (LAYOUT == L_SPARSE) {
     const int32_t e[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -357,7 +355,7 @@ __device__ __forceinline__ void put_piece(const SysDev& s, const BinLds& L, uint
 // Entries per 16-byte piece of a contiguous row, and pieces whose entries
 // one lane puts together.
 template <int LAYOUT>
-constexpr int kEpp = LAYOUT == L_ELL ? 2 : 4;
+constexpr int kEpp = 4;
 template <int LAYOUT>
 constexpr int kGroup = 8 / kEpp<LAYOUT>;
 
@@ -366,14 +364,7 @@ constexpr int kGroup = 8 / kEpp<LAYOUT>;
 template <int LAYOUT>
 __device__ __forceinline__ void collect_piece(const int4& x, int32_t lo, int32_t hi, int32_t v, int64_t col0,
                                               int32_t* t, int32_t* w, uint32_t& okm, int base) {
-  if (LAYOUT == L_ELL) {
-    t[base] = x.x;
-    w[base] = x.y;
-    t[base + 1] = x.z;
-    w[base + 1] = x.w;
-    okm |= (uint32_t)(lo <= 0 && hi > 0 && x.x >= 0) << base;
-    okm |= (uint32_t)(lo <= 1 && hi > 1 && x.z >= 0) << (base + 1);
-  } else {
+  {
     const int32_t e[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -518,7 +509,7 @@ __device__ __forceinline__ void block_walk_long(const SysDev& s, const BinLds& L
           if (LAYOUT == L_OPT) x = make_int2(s.sy[(int64_t)jj * s.q + e[0]], e[2]);
           else if (LAYOUT == L_SLICED)
             x = make_int2(s.sy[s.sy_off[e[0] / SLICE] + e[0] % SLICE + (int64_t)jj * SLICE], e[2]);
-          else x = s.ell[ell_index(s, e[0], jj + 1)];
+          else x = ell_pair(s, ell_index(s, e[0], jj + 1));
           pc[u].x = make_int4(x.x, x.y, x.x, x.y);
           pc[u].lo = 0;
           pc[u].hi = 1;
@@ -545,7 +536,7 @@ __device__ __forceinline__ int2 bin_entry(const SysDev& s, int32_t i, int32_t ru
                                           int32_t jj) {
   if (LAYOUT == L_OPT) return make_int2(s.sy[(int64_t)jj * s.q + i], v);
   if (LAYOUT == L_SLICED) return make_int2(s.sy[e0 + (int64_t)jj * SLICE], v);
-  return s.ell[ell_index(s, rule, jj + 1)];
+  return ell_pair(s, ell_index(s, rule, jj + 1));
 }
 
 // Entries jb .. jb + BIN_ROWS - 1 of the row of neuron i into x, target -1

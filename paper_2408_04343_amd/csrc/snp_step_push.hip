@@ -113,7 +113,7 @@ __device__ __forceinline__ void push_body(const SysDev& s, int32_t tile, int32_t
       }
     } else if (LAYOUT == L_ELL) {
       for (int32_t r = 1; r <= s.z; ++r) {
-        const int2 pr = s.ell[ell_index(s, o.erule, r)];
+        const int2 pr = ell_pair(s, ell_index(s, o.erule, r));
         if (pr.x < 0) break;
         atomicAdd(&cur[pr.x], pr.y);
         ++deg;
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(PW_NT) emit_push_wide_kernel(SysDev s, int32_t
       for (int32_t r = lane; r < deg; r += 64) atomicAdd(&cur[s.sy[b0 + (int64_t)r * SLICE]], v);
     } else if (LAYOUT == L_ELL) {
       for (int32_t r = lane; r < deg; r += 64) {
-        const int2 pr = s.ell[ell_index(s, rule, r + 1)];
+        const int2 pr = ell_pair(s, ell_index(s, rule, r + 1));
         atomicAdd(&cur[pr.x], pr.y);
       }
     } else {
