@@ -37,6 +37,18 @@ def test_algorithmic_bytes_per_layout():
     assert bench.alg_bytes("csr_pull", q, c, R) == state + 280 + 8 * q
 
 
+def test_packed_bytes_count_the_kernels_encodings():
+    c = {"emit_edges": 100, "emitting": 10, "reopening": 3, "rules_of_open": 50, "recv_in_edges": 70}
+    q, R = 1000, 4
+    state = 22 * q + R * 50 + 8 * 3
+    push = 8 * q + 4 * 100
+    # the ELL step reads the neuron plane of the pairs only, 4 bytes an entry
+    assert bench.packed_bytes("ell", q, c, R, 2) == state + push + 4 * 110
+    assert bench.packed_bytes("ell", q, c, R, 2) == bench.packed_bytes("optimized", q, c, R, 2)
+    assert bench.packed_bytes("csr_push", q, c, R, 2) == state + push + 4 * 100 + 8 * 10
+    assert bench.packed_bytes("csr_pull", q, c, R, 2) == state + 4 * q + 4 * 70 + 2 * (2 * q // 8)
+
+
 def test_workload_label_names_the_timed_steps():
     sp = wl.config1()
     lab = bench.workload_label(sp, 1000, 64)
