@@ -47,7 +47,8 @@ extern "C" {
  *              padding; p taken from the rule vector (Table 3).
  *   ELL        M^s_Pi: z' = MaxOutDegree + 1 rows x m columns of
  *              (neuron, value) pairs; row 0 = (own neuron, -c), then
- *              (target, +p), then (-1, 0) padding (Table 2).
+ *              (target, +p), then (-1, 0) padding (Table 2); kept on the
+ *              device as a plane of neurons and a plane of values.
  *   CSR_PUSH   out-neighbour lists (row starts + target ids, Sec. 3); spikes
  *              are pushed to targets.
  *   CSR_PULL   in-neighbour lists; each target gathers what its
