@@ -364,8 +364,10 @@ def skewed_check(binding, spec, layouts, steps):
     t0 = time.time()
     o = orc.OracleSystem(spec.q, spec.spikes0, spec.rules, spec.src, spec.dst, orc.SEM_STANDARD,
                          spec.select, spec.seed)
+    t1 = time.time()
     ref = [int(x) for x in o.step_record(steps, want_state=False)["digests"]]
     o.close()
+    step_s = time.time() - t1
     oracle_s = time.time() - t0
     res = {}
     for lay in layouts:
@@ -374,7 +376,11 @@ def skewed_check(binding, spec, layouts, steps):
         res[lay] = bool([int(x) for x in g.read_digests(0, steps)] == ref)
         g.close()
     log("config3 digests of %d steps vs oracle (%.1f s): %s" % (steps, oracle_s, res))
-    return {"steps": steps, "equal_to_oracle": res, "oracle_s": round(oracle_s, 1)}
+    cpu = {"value": spec.q * steps / step_s if step_s > 0 else None, "unit": "neuron-updates/s", "cores": 1,
+           "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
+           "sample": "config3-skewed: the first %d steps (the digest check), single-threaded C oracle "
+                     "(%.1f s of steps)" % (steps, step_s)}
+    return {"steps": steps, "equal_to_oracle": res, "oracle_s": round(oracle_s, 1), "cpu_baseline": cpu}
 
 
 def run_skewed(binding, torch, steps=500, warmup=16,
@@ -436,6 +442,7 @@ def run_skewed(binding, torch, steps=500, warmup=16,
                         "avg_launch_us": round(v["ms_per_step"] * 1e3, 3)}
     if check_steps > 0:
         out["parity"] = skewed_check(binding, spec, [k for k in ok], check_steps)
+        out["cpu_baseline"] = out["parity"].pop("cpu_baseline")
     return out
 
 
