@@ -330,8 +330,21 @@ __device__ __forceinline__ int64_t row_first(const SysDev& s, int32_t key) {
   return key;
 }
 
-__device__ __forceinline__ int32_t row_pieces(int64_t e0, int32_t n, int lg) {
-  return n > 0 ? (int32_t)(((e0 + n - 1) >> lg) - (e0 >> lg) + 1) : 0;
+// Low 32 bits of row_first, enough for where the row starts inside its
+// first piece (the arithmetic of a piece stays in 32 bits; only its address
+// is 64-bit).
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t row_first_lo(const SysDev& s, int32_t key) {
+  if (LAYOUT == L_ELL) return (uint32_t)key * (uint32_t)((s.z + 2) & ~1) + 1u;
+  if (LAYOUT == L_OPT) return (uint32_t)key * (uint32_t)((s.z + 3) & ~3);
+  if (LAYOUT == L_SPARSE) return (uint32_t)key * (uint32_t)s.q;
+  return (uint32_t)key;
+}
+
+// Pieces of 4 entries covering the n entries of the row with key `key`.
+template <int LAYOUT>
+__device__ __forceinline__ int32_t row_pieces(const SysDev& s, int32_t key, int32_t n) {
+  return n > 0 ? (int32_t)(((row_first_lo<LAYOUT>(s, key) & 3u) + (uint32_t)n - 1u) >> 2) + 1 : 0;
 }
 
 // Delivers the entries lo .. hi-1 of piece x (value v unless the layout
@@ -393,16 +406,15 @@ struct Piece {
 template <int LAYOUT>
 __device__ __forceinline__ Piece load_piece(const SysDev& s, int32_t key, int32_t n, int32_t v,
                                             int32_t first_piece_of_row, int32_t f) {
-  constexpr int lg = kLg<LAYOUT>;
-  const int64_t e0 = row_first<LAYOUT>(s, key);
-  const int64_t p = (e0 >> lg) + (f - first_piece_of_row);
+  const int32_t j = f - first_piece_of_row;                          // piece of the row
+  const int32_t r0 = (int32_t)(row_first_lo<LAYOUT>(s, key) & 3u);   // row start in its first piece
+  const int64_t p = (row_first<LAYOUT>(s, key) >> 2) + j;
   Piece o;
   o.x = row_base<LAYOUT>(s)[p];
-  const int64_t eb = p << lg;
-  o.lo = (int32_t)(e0 > eb ? e0 - eb : 0);
-  o.hi = (int32_t)(e0 + n - eb < (1 << lg) ? e0 + n - eb : (1 << lg));
+  o.lo = j == 0 ? r0 : 0;
+  o.hi = min(r0 + n - 4 * j, 4);
   o.v = v;
-  o.col0 = eb - e0;
+  o.col0 = 4 * j - r0;
   return o;
 }
 
@@ -416,7 +428,7 @@ __device__ __forceinline__ void wave_walk(const SysDev& s, const BinLds& L, uint
   int32_t* wk = L.wl + (threadIdx.x >> 6) * BIN_WL;
   int32_t* wn = wk + 64;
   int32_t* wi = wk + 128;
-  const int32_t np = on ? row_pieces(row_first<LAYOUT>(s, key), n, lg) : 0;
+  const int32_t np = on ? row_pieces<LAYOUT>(s, key, n) : 0;
   const int32_t inc = wave_incl_scan(np);
   const int32_t T = __shfl(inc, 63, 64);
   if (T == 0) return;
@@ -437,7 +449,7 @@ __device__ __forceinline__ void wave_walk(const SysDev& s, const BinLds& L, uint
         for (int st = 32; st >= 1; st >>= 1) o += (wi[o + st - 1] <= f) ? st : 0;
         const int32_t ko = wk[o], nv = wn[o], io = wi[o];
         const int32_t no = nv & 0xFFF;
-        const int32_t po = row_pieces(row_first<LAYOUT>(s, ko), no, lg);
+        const int32_t po = row_pieces<LAYOUT>(s, ko, no);
         pc[u] = load_piece<LAYOUT>(s, ko, no, nv >> 12, io - po, f);
       }
     }
@@ -470,7 +482,7 @@ __device__ __forceinline__ void block_walk_long(const SysDev& s, const BinLds& L
       np[x] = 0;
       if (h < nh) {
         const int32_t* e = L.hl + 4 * h;
-        np[x] = contig ? row_pieces(row_first<LAYOUT>(s, e[0]), e[1], lg) : e[1];
+        np[x] = contig ? row_pieces<LAYOUT>(s, e[0], e[1]) : e[1];
       }
       sum += np[x];
     }
@@ -499,7 +511,7 @@ __device__ __forceinline__ void block_walk_long(const SysDev& s, const BinLds& L
         }
         const int32_t* e = L.hl + 4 * o;
         if (kCanContig<LAYOUT> && contig) {
-          const int32_t po = row_pieces(row_first<LAYOUT>(s, e[0]), e[1], lg);
+          const int32_t po = row_pieces<LAYOUT>(s, e[0], e[1]);
           pc[u] = load_piece<LAYOUT>(s, e[0], e[1], e[2], e[3] - po, f);
         } else if constexpr (kCanStrided<LAYOUT>) {
           // entry jj of a strided row (neuron or rule slot e[0]) as a one-entry piece;
@@ -712,11 +724,10 @@ __device__ __forceinline__ void bin_body(const SysDev& s, int32_t tile, int32_t 
         n = LAYOUT == L_SPARSE ? s.q : deg[r];
       }
       constexpr int lg = kLg<LAYOUT>;
-      const bool light = em && n > 0 && row_pieces(row_first<LAYOUT>(s, key), n, lg) <= BIN_WAVE_PIECES;
+      const bool light = em && n > 0 && row_pieces<LAYOUT>(s, key, n) <= BIN_WAVE_PIECES;
       if (em && n > 0 && !light && !list_long(key, n, o[r].emit)) {
         // the block's list is full: this thread walks the row alone
-        const int64_t e0 = row_first<LAYOUT>(s, key);
-        const int32_t np = row_pieces(e0, n, lg);
+        const int32_t np = row_pieces<LAYOUT>(s, key, n);
         for (int32_t f = 0; f < np; ++f) {
           const Piece pc = load_piece<LAYOUT>(s, key, n, o[r].emit, 0, f);
           put_piece<LAYOUT>(s, L, gb, pc.x, pc.lo, pc.hi, pc.v, pc.col0);
