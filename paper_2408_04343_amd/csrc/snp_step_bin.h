@@ -455,6 +455,7 @@ __device__ __forceinline__ void wave_walk(const SysDev& s, const BinLds& L, uint
     }
 #pragma unroll
     for (int g = 0; g < BIN_U; g += kGroup<LAYOUT>) {
+      if (f0 + 64 * g >= T) break;  // the wave has no piece from here on
       int32_t t[8], w[8];
       uint32_t okm = 0;
 #pragma unroll
