@@ -189,8 +189,12 @@ __device__ __forceinline__ void bin_receive(const SysDev& s, int32_t tile, int32
     ex += rest[x];
   }
   if (tid == 0) L.pos[nb] = total;
+  // a wave whose first region is past the last adds nothing
+  const int32_t wave0 = (int32_t)(tid & ~63);
+  if (BIN_RPT * wave0 < nb) {
 #pragma unroll
-  for (int x = 0; x < BIN_RPT; ++x) add_chunk(L.acc, h[x], H, min(R, cnt[x] + H), b2);
+    for (int x = 0; x < BIN_RPT; ++x) add_chunk(L.acc, h[x], H, min(R, cnt[x] + H), b2);
+  }
   __syncthreads();
   for (int32_t e0 = tid; e0 < total; e0 += BIN_U * BIN_NT) {
     uint4 rv[BIN_U];
@@ -214,7 +218,10 @@ __device__ __forceinline__ void bin_receive(const SysDev& s, int32_t tile, int32
       }
     }
 #pragma unroll
-    for (int u = 0; u < BIN_U; ++u) add_chunk(L.acc, rv[u], 0, hi[u], b2);
+    for (int u = 0; u < BIN_U; ++u) {
+      if (e0 - (tid & 63) + u * BIN_NT >= total) break;  // the wave's chunks end here
+      add_chunk(L.acc, rv[u], 0, hi[u], b2);
+    }
   }
 }
 
