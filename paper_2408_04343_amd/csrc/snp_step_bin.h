@@ -41,16 +41,24 @@ static_assert(bin_union_word(BIN_MAX_TILES) + BIN_TILE + 3 * BIN_MAX_TILES + 1 +
               "binned LDS too small for the reception arrays");
 static_assert(bin_stage_chunks(BIN_MAX_TILES) >= BIN_MAX_TILES, "binned stage too small");
 
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active), in
+// registers: shifts within each row of 16 lanes, then the last lane of a row
+// broadcast to the rows after it.
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 // Exclusive prefix sum of v over the block; *total = the sum of all v.
 template <int NT>
 __device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* wsum, int32_t* total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
+  const int32_t x = wave_incl_scan(v);
   if (lane == 63) wsum[wv] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -65,16 +73,6 @@ __device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* wsum, int32_
   __syncthreads();
   *total = wsum[NT / 64];
   return wsum[wv] + x - v;
-}
-
-__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  return x;
 }
 
 // LDS written by some lanes of a wave and read by others: the wave's LDS
